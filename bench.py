@@ -1,0 +1,195 @@
+"""Benchmark: one MAHI evaluation (E, F, dE/dlambda-tilde) of the paper-scale system.
+
+Workload: periodic 21.5 nm cube of 333,400 rigid waters plus 512 two-form
+titratable sites of 8 atoms (1,004,296 atoms), octree depth 5, multipole
+order 8, float32 bulk arithmetic with float64 lattice, site correction and
+reductions.  Inputs are seeded synthetic data and stay resident in HBM; every
+timed evaluation writes E, F[N] and dV/dlambda-tilde to device memory.
+
+Reported next to the headline ns/eval:
+  * the float64 GPU path on the same system (FP32 speedup),
+  * the plain FMM on the same scaled charges with no sites (MAHI overhead %),
+  * per-stage mean durations from HIP events recorded on the library's stream
+    over the timed region, and the roofline of the dominant kernel (M2L),
+  * the CPU oracle on a bounded sample (same recipe, smaller cube), scaled to
+    the full system by the oracle's measured size exponent.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_FP32_MATRIX_TFLOPS = 157.3
+PEAK_FP64_MATRIX_TFLOPS = 78.6
+PEAK_FP32_VECTOR_TFLOPS = 157.3
+
+
+def m2l_translations(depth: int, periodic: bool) -> int:
+    lmin = 1 if periodic else 2
+    return sum(189 * 8 ** l for l in range(lmin, depth + 1))
+
+
+def p2p_pairs(system, depth: int) -> int:
+    """Ordered near-field pairs (i != j) over the 27 neighbour leaves."""
+    n = 2 ** depth
+    h = system.box / n
+    x = system.x.astype(np.float64) % system.box
+    c = np.minimum((x / h).astype(np.int64), n - 1)
+    cnt = np.zeros((n, n, n), dtype=np.int64)
+    np.add.at(cnt, (c[:, 0], c[:, 1], c[:, 2]), 1)
+    nb = np.zeros_like(cnt)
+    for dx in (-1, 0, 1):
+        for dy in (-1, 0, 1):
+            for dz in (-1, 0, 1):
+                nb += np.roll(np.roll(np.roll(cnt, dx, 0), dy, 1), dz, 2)
+    return int((cnt * nb).sum() - system.n_atoms)
+
+
+def time_evals(m, x_dev, out, steps, warmup, profile=False):
+    import torch
+    for _ in range(warmup):
+        m.eval_device(x_dev.data_ptr(), out["E"].data_ptr(), out["F"].data_ptr(),
+                      out["dvdl"].data_ptr() if out["dvdl"] is not None else 0)
+    torch.cuda.synchronize()
+    if profile:
+        m.profile_begin(steps)
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        m.eval_device(x_dev.data_ptr(), out["E"].data_ptr(), out["F"].data_ptr(),
+                      out["dvdl"].data_ptr() if out["dvdl"] is not None else 0)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    stages = m.profile_end()[0] if profile else None
+    return dt / steps, stages
+
+
+def cpu_baseline(full_n: int):
+    """Oracle (Ewald HI, float64, all host cores) on two smaller cubes of the same
+    recipe; the full-size time is extrapolated with the fitted size exponent."""
+    from oracle import hi
+    from synth import make_system
+    cores = os.cpu_count() or 1
+    pts = []
+    for edge in (4.0, 5.5):
+        nw = int(round(33.4 * edge ** 3))
+        ns = max(1, int(round(3 * nw / 1960)))
+        s = make_system(nw, edge, True, [8] * ns, [2] * ns, total_step=1.0, depth=3, seed=7)
+        t0 = time.perf_counter()
+        hi.hi_periodic(s.x, s.q, s.sites, s.box)
+        pts.append((s.n_atoms, time.perf_counter() - t0))
+    (n1, t1), (n2, t2) = pts
+    expo = float(np.log(t2 / t1) / np.log(n2 / n1))
+    t_full = t2 * (full_n / n2) ** expo
+    return {"value": t_full * 1e9, "unit": "ns/eval", "cores": cores, "kind": "oracle",
+            "sample": f"full HI evaluation of {n1} and {n2}-atom cubes of the same recipe "
+                      f"({t1:.2f}s, {t2:.2f}s); scaled to {full_n} atoms with exponent {expo:.2f}"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--config", type=int, default=2)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: the hot path runs on one MI355X (no multi-GPU path).",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_2410_01754_amd as pkg
+    from synth import make_config
+
+    s = make_config(args.config)
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream().cuda_stream
+    print(f"[bench] {s.name}: N={s.n_atoms} sites={len(s.sites)} forms={s.n_forms} d={s.depth} p={s.order}",
+          file=sys.stderr, flush=True)
+
+    def outputs(dtype, nforms):
+        return {"E": torch.zeros(1, dtype=torch.float64, device=dev),
+                "F": torch.zeros((s.n_atoms, 3), dtype=dtype, device=dev),
+                "dvdl": torch.zeros(max(nforms, 1), dtype=torch.float64, device=dev) if nforms else None}
+
+    # headline: float32 MAHI
+    m32 = pkg.from_system(s, precision=32, stream=stream)
+    x32 = torch.from_numpy(s.x).to(dev)
+    o32 = outputs(torch.float32, s.n_forms)
+    t32, stages = time_evals(m32, x32, o32, args.steps, args.warmup, profile=True)
+    print(f"[bench] fp32 MAHI {t32 * 1e3:.3f} ms/eval stages {stages}", file=sys.stderr, flush=True)
+
+    # plain FMM: same scaled charges as ordinary charges, no sites
+    qt = s.q.copy()
+    for st in s.sites:
+        qt[st.atoms] = st.lam @ st.charges
+    mp = pkg.Mahi(s.box, True, qt, [], order=s.order, depth=s.depth, precision=32, stream=stream)
+    op = outputs(torch.float32, 0)
+    tplain, _ = time_evals(mp, x32, op, args.steps, args.warmup)
+    mp.close()
+    print(f"[bench] fp32 plain FMM {tplain * 1e3:.3f} ms/eval", file=sys.stderr, flush=True)
+
+    # float64 path
+    m64 = pkg.from_system(s, precision=64, stream=stream)
+    x64 = torch.from_numpy(s.x.astype(np.float64)).to(dev)
+    o64 = outputs(torch.float64, s.n_forms)
+    t64, _ = time_evals(m64, x64, o64, max(3, args.steps // 4), 1)
+    m64.close()
+    print(f"[bench] fp64 MAHI {t64 * 1e3:.3f} ms/eval", file=sys.stderr, flush=True)
+
+    trans = m2l_translations(s.depth, True)
+    K = (s.order + 1) ** 2
+    m2l_flop = 2.0 * trans * K * K
+    m2l_s = stages["m2l"] * 1e-3
+    achieved = m2l_flop / m2l_s / 1e12
+    pairs = p2p_pairs(s, s.depth)
+    extra = {
+        "stage_ms": {k: round(v, 4) for k, v in stages.items()},
+        "fp64_ns_per_eval": t64 * 1e9,
+        "fp32_speedup_over_fp64": t64 / t32,
+        "plain_fmm_ns_per_eval": tplain * 1e9,
+        "mahi_overhead_pct": 100.0 * (t32 / tplain - 1.0),
+        "m2l_translations": trans,
+        "p2p_pairs": pairs,
+        "p2p_gflops": 20.0 * pairs / (stages["p2p_l2p"] * 1e-3) / 1e9,
+    }
+    line = {
+        "metric": "ns/eval (E,F,dV/dlambda) at 1M atoms+512 sites, FP32 vs FP64, MAHI overhead %",
+        "value": t32 * 1e9,
+        "unit": "ns/eval",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": t32 * 1e3,
+        "higher_is_better": False,
+        "scaling": "strong",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "periodic 21.5 nm cube, 333,400 rigid waters + 512 two-form 8-atom sites "
+                               "(1,004,296 atoms), depth 5, order 8", "n_atoms": s.n_atoms,
+                   "sites": len(s.sites), "forms": s.n_forms, "depth": s.depth, "order": s.order},
+        "roofline": {"bound": "mfma", "achieved": achieved, "peak": PEAK_FP32_MATRIX_TFLOPS, "unit": "TFLOP/s",
+                     "frac": achieved / PEAK_FP32_MATRIX_TFLOPS, "traffic": None,
+                     "kernel": "m2l", "flop_per_launch": m2l_flop},
+        "extra": extra,
+    }
+    m32.close()
+    if not args.no_cpu:
+        line["cpu_baseline"] = cpu_baseline(s.n_atoms)
+    print(json.dumps(line))
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,177 @@
+/*
+ * mahi.h - C ABI of the MI355X MAHI library (libmahi.so).
+ *
+ * Multipole-Accelerated Hamiltonian Interpolation (Kohnke, Briand, Kutzner,
+ * Grubmueller, arXiv 2410.01754): one fast-multipole Coulomb evaluation of the
+ * lambda-tilde scaled charges in a cubic box, followed by a per-site correction
+ * that turns the charge-scaled result into the exact Hamiltonian-interpolation
+ * (HI) energy, atom forces and per-form derivatives dE/dlambda-tilde.
+ *
+ * Problem statement (paper, Theory):
+ *   - N point charges in a cube of edge L, periodic in all three directions
+ *     (eq nbody_periodic) or with open boundaries;
+ *   - M titratable sites; site s owns n_s atoms and f_s forms, form r giving
+ *     those atoms the charges q^(s,r) (section "Hamiltonian Interpolation
+ *     Formulation");
+ *   - per-form weights lambda-tilde (eq lambda_tilde, constraint eq
+ *     constraint); site-atom charges become qt = sum_r lt_r q^(s,r);
+ *   - outputs: the HI energy of the general formulation (eq iter_ham_lambda),
+ *     forces F = -dE/dx and dE/dlambda-tilde per form (the per-form part of the
+ *     mapping K of section "Calculation of Forces on lambda Particles").
+ * Periodic energies are Ewald energies with tin-foil boundaries (section
+ * "Multipole-Accelerated Hamiltonian Interpolation", eq approx_nbody_periodic)
+ * and, for a charged cell, a uniform neutralising background.
+ *
+ * Conventions
+ *   Units: nm and elementary charges; energies are scaled by coulomb_k
+ *     (default 138.9354576 kJ mol^-1 nm e^-2).
+ *   Ownership: the caller owns every array it passes.  mahi_create copies the
+ *     charges and site tables; no call keeps a pointer after it returns.  The
+ *     context owns all device memory (allocated once, in mahi_create).
+ *   Errors: every call returns a mahi_status.  Argument checks run before any
+ *     device work, so invalid input never reaches the GPU; on error no output
+ *     is written.  mahi_last_error() gives a message for the last failure on a
+ *     context.  No call aborts the process.
+ *   Threads: one context may be used by one host thread at a time.
+ *   Determinism: identical inputs give bit-identical outputs (no floating-point
+ *     atomics; all reductions run in a fixed order).
+ */
+#ifndef MAHI_H
+#define MAHI_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct mahi_ctx mahi_ctx; /* opaque; owned by the library */
+
+typedef enum {
+  MAHI_OK = 0,
+  MAHI_EINVAL = -1,        /* bad argument (null pointer, size, non-finite value, bad site table) */
+  MAHI_ENOMEM = -2,        /* host or device allocation failed */
+  MAHI_EDEVICE = -3,       /* HIP runtime error or no usable gfx950 device */
+  MAHI_ERANGE = -4,        /* value outside the supported range (order, depth, forms, atoms per site) */
+  MAHI_ESTATE = -5,        /* call out of order (mahi_eval before mahi_set_lambda) */
+  MAHI_EUNSUPPORTED = -6   /* feature not available in this build */
+} mahi_status;
+
+/* Simulation cell: a cube (the paper's method supports cubic boxes only). */
+typedef struct {
+  double edge;   /* periodic: cube edge L > 0 (nm).  open: ignored; the root
+                    cube of the octree is the bounding cube of each call's
+                    coordinates */
+  int periodic;  /* 1: periodic in x, y, z;  0: open boundaries */
+} mahi_box;
+
+/* Titratable sites.  Site s owns atoms_per_site[s] atoms (indices into the
+ * N atoms, pairwise disjoint over all sites) and forms_per_site[s] forms.
+ * form_charges holds, site after site, the charges of form 0 for every atom
+ * of the site, then form 1, ... (form-major, atom-minor), in e.            */
+typedef struct {
+  int32_t n_sites;                /* M >= 0 */
+  const int32_t *forms_per_site;  /* [M], each in 1..16 */
+  const int32_t *atoms_per_site;  /* [M], each in 1..32 */
+  const int32_t *site_atoms;      /* [sum atoms_per_site] */
+  const double *form_charges;     /* [sum forms_per_site * atoms_per_site] */
+} mahi_sites;
+
+typedef struct {
+  int order;         /* multipole order p: degrees 0..p, (p+1)^2 real coefficients; 1..20 */
+  int depth;         /* octree depth d (8^d leaves); 0..7 */
+  int precision;     /* 32: float32 arithmetic in the bulk FMM (lattice, site
+                        correction and reductions stay float64);
+                        64: float64 everywhere */
+  double coulomb_k;  /* energy scale; <= 0 selects 138.9354576 */
+  void *hip_stream;  /* hipStream_t to run on; NULL = a stream created by the context */
+} mahi_opts;
+
+/* mahi_eval flags */
+#define MAHI_DEVICE_IO 1u /* every pointer in mahi_eval_args is device memory and the
+                             call returns without waiting for the GPU (the caller
+                             synchronises the stream) */
+
+typedef struct {
+  const void *xyz;    /* [N][3] positions (nm); float when precision = 32, double when 64.
+                         periodic: any finite values (wrapped into the cell);
+                         open: any finite values */
+  double *energy;     /* [1] HI energy; may be NULL */
+  void *forces;       /* [N][3] F = -dE/dx, same type as xyz; may be NULL */
+  double *dvdl;       /* [sum forms] dE/dlambda-tilde per form, site-major; may be NULL */
+  void *potential;    /* [N] coulomb_k * charge-scaled potential at each atom (the
+                         potential of the charge-scaled Hamiltonian, including
+                         the atom's own periodic images), same type as xyz; may be NULL */
+  uint32_t flags;     /* 0 or MAHI_DEVICE_IO */
+} mahi_eval_args;
+
+/* Create a context: validates everything, chooses no parameters on its own,
+ * generates the translation and lattice tables in float64 on the host, and
+ * allocates all device buffers.  charges[N] are the environment charges;
+ * entries at site atoms are ignored.  sites may be NULL (plain FMM).       */
+mahi_status mahi_create(mahi_ctx **out, const mahi_box *box, int64_t n_atoms, const double *charges,
+                        const mahi_sites *sites, const mahi_opts *opts);
+
+/* Set the per-form weights lambda-tilde[sum forms] (site-major, then form).
+ * Values are used as given (no renormalisation; the formulation stays exact
+ * off the simplex).  Non-finite values give MAHI_EINVAL.  Runs the charge
+ * scaling on the device.                                                    */
+mahi_status mahi_set_lambda(mahi_ctx *ctx, const double *lambda_tilde);
+
+/* One evaluation: octree build, P2M, M2M, periodic lattice, M2L, L2L, L2P and
+ * P2P on the scaled charges, then the per-site correction (paper, section
+ * "Multipole-Accelerated Hamiltonian Interpolation": eqs correction_scheme to
+ * C_B and the execution order of section "Execution of MAHI").
+ * Without MAHI_DEVICE_IO the call copies host inputs and outputs and waits
+ * for the GPU.                                                              */
+mahi_status mahi_eval(mahi_ctx *ctx, const mahi_eval_args *args);
+
+/* Release every host and device resource of the context (NULL is allowed). */
+void mahi_destroy(mahi_ctx *ctx);
+
+const char *mahi_strerror(mahi_status s);
+const char *mahi_last_error(const mahi_ctx *ctx);
+
+/* Sizes a context was created with: n_atoms, n_sites, total forms, order,
+ * depth, precision (NULL pointers are skipped).                              */
+mahi_status mahi_info(const mahi_ctx *ctx, int64_t *n_atoms, int32_t *n_sites, int32_t *n_forms, int *order,
+                      int *depth, int *precision);
+
+/* Host-only checks of the float64 operator tables against direct sums
+ * (translations, lattice coefficients); no device is touched.  Writes the
+ * largest relative deviation found to *max_rel_err.                         */
+mahi_status mahi_host_selftest(int order, double *max_rel_err);
+
+/* Device check of the matrix-core tile layout used by the M2L contraction:
+ * multiplies random matrices with the kernel's tile code and compares with a
+ * host product.  precision 32 or 64.  Writes the largest relative error.     */
+mahi_status mahi_device_selftest(int precision, double *max_rel_err);
+
+/* Stage timing.  Between mahi_profile_begin and mahi_profile_end the library
+ * records HIP events on its stream at every stage boundary of up to max_evals
+ * evaluations (no extra synchronisation).  mahi_profile_end waits for the
+ * stream and writes the mean duration in ms of each stage over the recorded
+ * evaluations to stage_ms[MAHI_N_STAGES] and their number to *n_evals.
+ * Stages: 0 octree build, 1 P2M, 2 M2M, 3 lattice, 4 M2L, 5 L2L,
+ * 6 P2P + L2P + outputs, 7 site correction, 8 energy reduction.             */
+#define MAHI_N_STAGES 9
+mahi_status mahi_profile_begin(mahi_ctx *ctx, int max_evals);
+mahi_status mahi_profile_end(mahi_ctx *ctx, double *stage_ms, int *n_evals);
+const char *mahi_stage_name(int stage);
+
+/* Test hook: copy an internal buffer of the last evaluation to host memory.
+ * which: 0 multipoles (all levels, level 0 first, boxes in Morton order,
+ *          (order+1)^2 coefficients each), 1 local expansions (same layout),
+ *        2 leaf start offsets (int32, 8^depth + 1), 3 sorted-to-user atom
+ *          permutation (int32, N), 4 sorted atoms (leaf-local x, y, z and
+ *          scaled charge per atom).
+ * Elements are float or double as the context's precision (ints for 2, 3).
+ * count is the number of elements to copy; MAHI_ERANGE if it exceeds the
+ * buffer.  Waits for the context's stream.                                  */
+mahi_status mahi_debug_copy(mahi_ctx *ctx, int which, void *host_out, int64_t count);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MAHI_H */

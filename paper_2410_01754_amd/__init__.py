@@ -1,0 +1,6 @@
+"""MI355X-native Multipole-Accelerated Hamiltonian Interpolation (MAHI).
+
+The compute path is libmahi.so (HIP kernels for gfx950, C ABI in
+include/mahi.h); this package is its Python binding.
+"""
+from .mahi import Mahi, MahiError, device_selftest, from_system, host_selftest, lib  # noqa: F401

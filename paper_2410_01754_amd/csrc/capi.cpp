@@ -1,0 +1,617 @@
+// C ABI of libmahi.so (declared in include/mahi.h): validation, context
+// lifecycle, table upload and the launch sequence of one evaluation.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <random>
+#include <string>
+#include <vector>
+
+#include "../../include/mahi.h"
+#include "device_common.hpp"
+#include "kernels.hpp"
+#include "tables.hpp"
+
+using namespace mahi;
+
+namespace {
+
+constexpr double kDefaultKe = 138.9354576;
+constexpr int kSlots = 343;  // offsets v in [-3, 3]^3
+
+struct DevBuf {
+  void *p = nullptr;
+  size_t bytes = 0;
+};
+
+}  // namespace
+
+struct mahi_ctx {
+  int64_t N = 0;
+  int periodic = 1;
+  double edge = 0.0;
+  int p = 8, d = 0, prec = 32;
+  double ke = kDefaultKe;
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  int device = 0;
+  int M = 0, nforms = 0, nsite_atoms = 0, maxa = 0, maxf = 0;
+  bool lambda_set = false;
+  std::string err;
+  std::vector<DevBuf> bufs;
+
+  // device buffers (element type T = float or double for the FMM arrays)
+  void *xyz = nullptr, *qt = nullptr, *F = nullptr, *pot = nullptr, *phi_sorted = nullptr;
+  void *Mc = nullptr, *Lc = nullptr, *m2l = nullptr, *m2m = nullptr, *l2l = nullptr, *sorted = nullptr;
+  double *LamT = nullptr, *qds = nullptr, *epart = nullptr, *dE_site = nullptr, *dvdl = nullptr, *E = nullptr;
+  double *bbox = nullptr, *lam = nullptr, *fq = nullptr;
+  int4 *lists = nullptr;
+  Geom *geom = nullptr;
+  int *key = nullptr, *count = nullptr, *start = nullptr, *cursor = nullptr, *tmp = nullptr, *perm = nullptr,
+      *slot_of = nullptr;
+  int *atom_off = nullptr, *form_off = nullptr, *fq_off = nullptr, *site_atoms = nullptr;
+  int nbbox = 256;
+  // stage profiling: events[eval][stage boundary]
+  std::vector<hipEvent_t> prof_events;
+  int prof_max = 0, prof_n = 0;
+  void mark(int boundary) {
+    if (prof_n < prof_max) (void)hipEventRecord(prof_events[(size_t)prof_n * (MAHI_N_STAGES + 1) + boundary], stream);
+  }
+
+  mahi_status fail(mahi_status s, const std::string &m) {
+    err = m;
+    return s;
+  }
+  template <class P>
+  hipError_t alloc(P *&ptr, size_t bytes) {
+    void *q = nullptr;
+    hipError_t e = hipMalloc(&q, bytes < 16 ? 16 : bytes);
+    if (e != hipSuccess) return e;
+    bufs.push_back({q, bytes});
+    ptr = static_cast<P *>(q);
+    return hipSuccess;
+  }
+};
+
+namespace {
+
+thread_local std::string g_create_error;
+
+bool is_fin(double v) { return std::isfinite(v); }
+
+template <class T>
+void to_layout_transposed(int K, const std::vector<double> &rowmajor, T *out) {
+  // out[c][r] = T[r][c]
+  for (int r = 0; r < K; ++r)
+    for (int c = 0; c < K; ++c) out[(size_t)c * K + r] = (T)rowmajor[(size_t)r * K + c];
+}
+
+// The 8 parity-class interaction lists: target child c of parent P; sources are
+// the children of P's 27 neighbours that are not adjacent to the target.
+std::vector<int4> class_lists() {
+  std::vector<int4> out;
+  for (int c = 0; c < 8; ++c) {
+    const int cx = (c >> 2) & 1, cy = (c >> 1) & 1, cz = c & 1;
+    int cnt = 0;
+    for (int px = -1; px <= 1; ++px)
+      for (int py = -1; py <= 1; ++py)
+        for (int pz = -1; pz <= 1; ++pz)
+          for (int s = 0; s < 8; ++s) {
+            const int sx = (s >> 2) & 1, sy = (s >> 1) & 1, sz = s & 1;
+            const int vx = cx - (2 * px + sx), vy = cy - (2 * py + sy), vz = cz - (2 * pz + sz);
+            if (std::max(std::abs(vx), std::max(std::abs(vy), std::abs(vz))) <= 1) continue;
+            int4 e;
+            e.x = vx;
+            e.y = vy;
+            e.z = vz;
+            e.w = (vx + 3) * 49 + (vy + 3) * 7 + (vz + 3);
+            out.push_back(e);
+            ++cnt;
+          }
+    (void)cnt;
+  }
+  return out;
+}
+
+const char *hip_msg(hipError_t e) { return hipGetErrorString(e); }
+
+#define HIP_TRY(expr, what)                                                                 \
+  do {                                                                                      \
+    hipError_t _e = (expr);                                                                 \
+    if (_e != hipSuccess) return ctx->fail(MAHI_EDEVICE, std::string(what) + ": " + hip_msg(_e)); \
+  } while (0)
+
+template <class T>
+mahi_status setup_device(mahi_ctx *ctx, const std::vector<double> &q_env, const std::vector<int> &atom_off,
+                         const std::vector<int> &form_off, const std::vector<int> &fq_off,
+                         const std::vector<int> &site_atoms, const std::vector<double> &fq) {
+  const int p = ctx->p, d = ctx->d, K = ncoef(p);
+  const int64_t N = ctx->N;
+  const int nleaf = 1 << (3 * d);
+  const int64_t nbox = level_offset(d + 1);
+  HIP_TRY(upload_constants(), "constant tables");
+  HIP_TRY(ctx->alloc(ctx->xyz, sizeof(T) * 3 * N), "alloc xyz");
+  HIP_TRY(ctx->alloc(ctx->qt, sizeof(T) * N), "alloc charges");
+  HIP_TRY(ctx->alloc(ctx->F, sizeof(T) * 3 * N), "alloc forces");
+  HIP_TRY(ctx->alloc(ctx->pot, sizeof(T) * N), "alloc potential");
+  HIP_TRY(ctx->alloc(ctx->phi_sorted, sizeof(T) * N), "alloc potential (sorted)");
+  HIP_TRY(ctx->alloc(ctx->sorted, sizeof(Atom4<T>) * N), "alloc sorted atoms");
+  HIP_TRY(ctx->alloc(ctx->Mc, sizeof(T) * nbox * K), "alloc multipoles");
+  HIP_TRY(ctx->alloc(ctx->Lc, sizeof(T) * nbox * K), "alloc locals");
+  HIP_TRY(hipMemset(ctx->Lc, 0, sizeof(T) * nbox * K), "zero locals");
+  HIP_TRY(ctx->alloc(ctx->key, sizeof(int) * N), "alloc keys");
+  HIP_TRY(ctx->alloc(ctx->tmp, sizeof(int) * N), "alloc scatter");
+  HIP_TRY(ctx->alloc(ctx->perm, sizeof(int) * N), "alloc perm");
+  HIP_TRY(ctx->alloc(ctx->slot_of, sizeof(int) * N), "alloc slot map");
+  HIP_TRY(ctx->alloc(ctx->count, sizeof(int) * nleaf), "alloc counts");
+  HIP_TRY(ctx->alloc(ctx->cursor, sizeof(int) * nleaf), "alloc cursors");
+  HIP_TRY(ctx->alloc(ctx->start, sizeof(int) * (nleaf + 1)), "alloc starts");
+  HIP_TRY(ctx->alloc(ctx->qds, sizeof(double) * 5 * nleaf), "alloc moments");
+  HIP_TRY(ctx->alloc(ctx->epart, sizeof(double) * p2p_blocks<T>(d)), "alloc energy partials");
+  HIP_TRY(ctx->alloc(ctx->E, sizeof(double) * 1), "alloc energy");
+  HIP_TRY(ctx->alloc(ctx->bbox, sizeof(double) * 6 * ctx->nbbox), "alloc bbox");
+  HIP_TRY(ctx->alloc(ctx->geom, sizeof(Geom)), "alloc geometry");
+  Geom g{};
+  g.edge = ctx->periodic ? ctx->edge : 1.0;
+  HIP_TRY(hipMemcpy(ctx->geom, &g, sizeof(Geom), hipMemcpyHostToDevice), "upload geometry");
+  {
+    std::vector<T> qh(N);
+    for (int64_t i = 0; i < N; ++i) qh[i] = (T)q_env[i];
+    HIP_TRY(hipMemcpy(ctx->qt, qh.data(), sizeof(T) * N, hipMemcpyHostToDevice), "upload charges");
+  }
+  // translation tables
+  {
+    std::vector<double> Tm((size_t)K * K);
+    std::vector<T> up((size_t)8 * K * K), dn((size_t)8 * K * K);
+    for (int s = 0; s < 8; ++s) {
+      const double delta[3] = {(((s >> 2) & 1) - 0.5) * 0.5, (((s >> 1) & 1) - 0.5) * 0.5, ((s & 1) - 0.5) * 0.5};
+      m2m_matrix(p, delta, Tm.data());
+      to_layout_transposed<T>(K, Tm, up.data() + (size_t)s * K * K);
+      l2l_matrix(p, delta, Tm.data());
+      to_layout_transposed<T>(K, Tm, dn.data() + (size_t)s * K * K);
+    }
+    HIP_TRY(ctx->alloc(ctx->m2m, sizeof(T) * up.size()), "alloc m2m");
+    HIP_TRY(ctx->alloc(ctx->l2l, sizeof(T) * dn.size()), "alloc l2l");
+    HIP_TRY(hipMemcpy(ctx->m2m, up.data(), sizeof(T) * up.size(), hipMemcpyHostToDevice), "upload m2m");
+    HIP_TRY(hipMemcpy(ctx->l2l, dn.data(), sizeof(T) * dn.size(), hipMemcpyHostToDevice), "upload l2l");
+  }
+  const int lmin = ctx->periodic ? 1 : 2;
+  if (d >= lmin) {
+    int KK, RP;
+    m2l_table_layout<T>(p, KK, RP);
+    std::vector<T> tab((size_t)kSlots * KK * RP, T(0));
+    std::vector<double> Tv((size_t)K * K);
+    for (int slot = 0; slot < kSlots; ++slot) {
+      const int vx = slot / 49 - 3, vy = (slot / 7) % 7 - 3, vz = slot % 7 - 3;
+      if (std::max(std::abs(vx), std::max(std::abs(vy), std::abs(vz))) <= 1) continue;
+      const double v[3] = {double(vx), double(vy), double(vz)};
+      m2l_matrix(p, v, Tv.data());
+      T *dst = tab.data() + (size_t)slot * KK * RP;
+      for (int r = 0; r < K; ++r)
+        for (int c = 0; c < K; ++c) dst[(size_t)c * RP + r] = (T)Tv[(size_t)r * K + c];
+    }
+    HIP_TRY(ctx->alloc(ctx->m2l, sizeof(T) * tab.size()), "alloc m2l table");
+    HIP_TRY(hipMemcpy(ctx->m2l, tab.data(), sizeof(T) * tab.size(), hipMemcpyHostToDevice), "upload m2l table");
+    std::vector<int4> lists = class_lists();
+    HIP_TRY(ctx->alloc(ctx->lists, sizeof(int4) * lists.size()), "alloc lists");
+    HIP_TRY(hipMemcpy(ctx->lists, lists.data(), sizeof(int4) * lists.size(), hipMemcpyHostToDevice), "upload lists");
+  }
+  {
+    std::vector<double> Lam((size_t)K * K, 0.0), LamT((size_t)K * K, 0.0);
+    if (ctx->periodic) lattice_matrix(p, Lam.data());
+    for (int r = 0; r < K; ++r)
+      for (int c = 0; c < K; ++c) LamT[(size_t)c * K + r] = Lam[(size_t)r * K + c];
+    HIP_TRY(ctx->alloc(ctx->LamT, sizeof(double) * LamT.size()), "alloc lattice");
+    HIP_TRY(hipMemcpy(ctx->LamT, LamT.data(), sizeof(double) * LamT.size(), hipMemcpyHostToDevice), "upload lattice");
+  }
+  // sites
+  if (ctx->M > 0) {
+    HIP_TRY(ctx->alloc(ctx->atom_off, sizeof(int) * atom_off.size()), "alloc sites");
+    HIP_TRY(ctx->alloc(ctx->form_off, sizeof(int) * form_off.size()), "alloc sites");
+    HIP_TRY(ctx->alloc(ctx->fq_off, sizeof(int) * fq_off.size()), "alloc sites");
+    HIP_TRY(ctx->alloc(ctx->site_atoms, sizeof(int) * site_atoms.size()), "alloc sites");
+    HIP_TRY(ctx->alloc(ctx->fq, sizeof(double) * fq.size()), "alloc sites");
+    HIP_TRY(ctx->alloc(ctx->lam, sizeof(double) * ctx->nforms), "alloc lambda");
+    HIP_TRY(ctx->alloc(ctx->dvdl, sizeof(double) * ctx->nforms), "alloc dvdl");
+    HIP_TRY(ctx->alloc(ctx->dE_site, sizeof(double) * ctx->M), "alloc site energies");
+    HIP_TRY(hipMemcpy(ctx->atom_off, atom_off.data(), sizeof(int) * atom_off.size(), hipMemcpyHostToDevice), "upload");
+    HIP_TRY(hipMemcpy(ctx->form_off, form_off.data(), sizeof(int) * form_off.size(), hipMemcpyHostToDevice), "upload");
+    HIP_TRY(hipMemcpy(ctx->fq_off, fq_off.data(), sizeof(int) * fq_off.size(), hipMemcpyHostToDevice), "upload");
+    HIP_TRY(hipMemcpy(ctx->site_atoms, site_atoms.data(), sizeof(int) * site_atoms.size(), hipMemcpyHostToDevice),
+            "upload");
+    HIP_TRY(hipMemcpy(ctx->fq, fq.data(), sizeof(double) * fq.size(), hipMemcpyHostToDevice), "upload");
+  }
+  return MAHI_OK;
+}
+
+template <class T>
+SiteArgs site_args(const mahi_ctx *ctx) {
+  SiteArgs s;
+  s.n_sites = ctx->M;
+  s.p = ctx->p;
+  s.K = ncoef(ctx->p);
+  s.periodic = ctx->periodic;
+  s.maxa = ctx->maxa;
+  s.maxf = ctx->maxf;
+  s.ke = ctx->ke;
+  s.atom_off = ctx->atom_off;
+  s.form_off = ctx->form_off;
+  s.fq_off = ctx->fq_off;
+  s.site_atoms = ctx->site_atoms;
+  s.fq = ctx->fq;
+  s.lam = ctx->lam;
+  return s;
+}
+
+template <class T>
+mahi_status eval_impl(mahi_ctx *ctx, const mahi_eval_args *a) {
+  const bool dev = (a->flags & MAHI_DEVICE_IO) != 0;
+  const int64_t N = ctx->N;
+  const int p = ctx->p, d = ctx->d, K = ncoef(p), nleaf = 1 << (3 * d);
+  hipStream_t st = ctx->stream;
+  HIP_TRY(hipSetDevice(ctx->device), "set device");
+  const T *xyz = static_cast<const T *>(a->xyz);
+  if (!dev) {
+    HIP_TRY(hipMemcpyAsync(ctx->xyz, a->xyz, sizeof(T) * 3 * N, hipMemcpyHostToDevice, st), "copy positions");
+    xyz = static_cast<const T *>(ctx->xyz);
+  }
+  T *F = dev ? static_cast<T *>(a->forces) : (a->forces ? static_cast<T *>(ctx->F) : nullptr);
+  T *pot = dev ? static_cast<T *>(a->potential) : (a->potential ? static_cast<T *>(ctx->pot) : nullptr);
+  double *E = (dev && a->energy) ? a->energy : ctx->E;
+  double *dvdl = (dev && a->dvdl) ? a->dvdl : ctx->dvdl;
+  if (ctx->M > 0 && !dvdl) dvdl = ctx->dvdl;
+
+  T *Mc = static_cast<T *>(ctx->Mc), *Lc = static_cast<T *>(ctx->Lc);
+  ctx->mark(0);
+  if (!ctx->periodic) launch_bbox<T>(xyz, N, ctx->bbox, ctx->nbbox, ctx->geom, st);
+  TreeBufs<T> tb{ctx->key, ctx->count, ctx->start, ctx->cursor, ctx->tmp, ctx->perm, ctx->slot_of,
+                 static_cast<Atom4<T> *>(ctx->sorted)};
+  launch_tree<T>(xyz, static_cast<const T *>(ctx->qt), N, ctx->geom, d, ctx->periodic, tb, st);
+  ctx->mark(1);
+  launch_p2m<T>(tb.sorted, ctx->start, nleaf, p, Mc + level_offset(d) * K, ctx->periodic ? ctx->qds : nullptr, ctx->geom,
+                d, st);
+  ctx->mark(2);
+  const int lmin = ctx->periodic ? 1 : 2;
+  const int mlow = ctx->periodic ? 0 : 2;
+  for (int l = d - 1; l >= mlow; --l) launch_m2m<T>(Mc, l, K, static_cast<const T *>(ctx->m2m), st);
+  ctx->mark(3);
+  if (ctx->periodic) launch_lattice<T>(Mc, Lc, ctx->LamT, K, ctx->qds, nleaf, ctx->geom, st);
+  ctx->mark(4);
+  if (d >= lmin)
+    launch_m2l<T>(Mc, Lc, static_cast<const T *>(ctx->m2l), ctx->lists, p, d, ctx->periodic, st);
+  ctx->mark(5);
+  for (int l = ctx->periodic ? 1 : 3; l <= d; ++l) launch_l2l<T>(Lc, l, K, static_cast<const T *>(ctx->l2l), st);
+  ctx->mark(6);
+  launch_p2p<T>(tb.sorted, ctx->start, ctx->perm, Lc + level_offset(d) * K, ctx->geom, d, ctx->periodic, p, ctx->ke,
+                static_cast<T *>(ctx->phi_sorted), F, pot, ctx->epart, st);
+  ctx->mark(7);
+  if (ctx->M > 0) {
+    SiteArgs s = site_args<T>(ctx);
+    launch_site<T>(s, xyz, ctx->slot_of, static_cast<const T *>(ctx->phi_sorted), ctx->geom, ctx->LamT, F, dvdl,
+                   ctx->dE_site, st);
+  }
+  ctx->mark(8);
+  launch_finalize(ctx->epart, p2p_blocks<T>(d), ctx->dE_site, ctx->M, ctx->ke, E, st);
+  ctx->mark(9);
+  if (ctx->prof_n < ctx->prof_max) ++ctx->prof_n;
+  HIP_TRY(hipGetLastError(), "kernel launch");
+  if (!dev) {
+    if (a->energy) HIP_TRY(hipMemcpyAsync(a->energy, ctx->E, sizeof(double), hipMemcpyDeviceToHost, st), "copy energy");
+    if (a->dvdl && ctx->M > 0)
+      HIP_TRY(hipMemcpyAsync(a->dvdl, ctx->dvdl, sizeof(double) * ctx->nforms, hipMemcpyDeviceToHost, st), "copy dvdl");
+    if (a->forces) HIP_TRY(hipMemcpyAsync(a->forces, ctx->F, sizeof(T) * 3 * N, hipMemcpyDeviceToHost, st), "copy forces");
+    if (a->potential)
+      HIP_TRY(hipMemcpyAsync(a->potential, ctx->pot, sizeof(T) * N, hipMemcpyDeviceToHost, st), "copy potential");
+    HIP_TRY(hipStreamSynchronize(st), "evaluation");
+  }
+  return MAHI_OK;
+}
+
+void free_ctx(mahi_ctx *ctx) {
+  if (!ctx) return;
+  (void)hipSetDevice(ctx->device);
+  if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
+  for (auto &e : ctx->prof_events) (void)hipEventDestroy(e);
+  for (auto &b : ctx->bufs) (void)hipFree(b.p);
+  if (ctx->own_stream && ctx->stream) (void)hipStreamDestroy(ctx->stream);
+  delete ctx;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *mahi_strerror(mahi_status s) {
+  switch (s) {
+    case MAHI_OK: return "ok";
+    case MAHI_EINVAL: return "invalid argument";
+    case MAHI_ENOMEM: return "out of memory";
+    case MAHI_EDEVICE: return "device error";
+    case MAHI_ERANGE: return "value out of supported range";
+    case MAHI_ESTATE: return "call out of order";
+    case MAHI_EUNSUPPORTED: return "unsupported";
+  }
+  return "unknown status";
+}
+
+const char *mahi_last_error(const mahi_ctx *ctx) {
+  if (!ctx) return g_create_error.c_str();
+  return ctx->err.c_str();
+}
+
+mahi_status mahi_create(mahi_ctx **out, const mahi_box *box, int64_t n_atoms, const double *charges,
+                        const mahi_sites *sites, const mahi_opts *opts) {
+  g_create_error.clear();
+  auto bad = [](mahi_status s, const std::string &m) {
+    g_create_error = m;
+    return s;
+  };
+  if (!out) return bad(MAHI_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (!box || !opts || !charges) return bad(MAHI_EINVAL, "box, opts and charges must not be NULL");
+  if (n_atoms < 1 || n_atoms > (int64_t)0x7fffffff - 1) return bad(MAHI_ERANGE, "n_atoms must be in 1..2^31-2");
+  if (box->periodic != 0 && box->periodic != 1) return bad(MAHI_EINVAL, "box.periodic must be 0 or 1");
+  if (box->periodic && !(is_fin(box->edge) && box->edge > 0)) return bad(MAHI_EINVAL, "periodic box edge must be > 0");
+  if (opts->order < 1 || opts->order > kMaxOrder) return bad(MAHI_ERANGE, "order must be in 1..20");
+  if (opts->depth < 0 || opts->depth > 7) return bad(MAHI_ERANGE, "depth must be in 0..7");
+  if (opts->precision != 32 && opts->precision != 64) return bad(MAHI_EINVAL, "precision must be 32 or 64");
+  if (!is_fin(opts->coulomb_k)) return bad(MAHI_EINVAL, "coulomb_k must be finite");
+  for (int64_t i = 0; i < n_atoms; ++i)
+    if (!is_fin(charges[i])) return bad(MAHI_EINVAL, "non-finite charge");
+  std::vector<double> q_env(charges, charges + n_atoms);
+  std::vector<int> atom_off{0}, form_off{0}, fq_off, site_atoms;
+  std::vector<double> fq;
+  int maxa = 0, maxf = 0;
+  const int M = sites ? sites->n_sites : 0;
+  if (sites) {
+    if (M < 0) return bad(MAHI_EINVAL, "n_sites must be >= 0");
+    if (M > 0 && (!sites->forms_per_site || !sites->atoms_per_site || !sites->site_atoms || !sites->form_charges))
+      return bad(MAHI_EINVAL, "site arrays must not be NULL");
+    std::vector<char> used(n_atoms, 0);
+    int64_t fo = 0;
+    for (int s = 0; s < M; ++s) {
+      const int nf = sites->forms_per_site[s], na = sites->atoms_per_site[s];
+      if (nf < 1 || nf > kMaxSiteForms) return bad(MAHI_ERANGE, "forms per site must be in 1..16");
+      if (na < 1 || na > kMaxSiteAtoms) return bad(MAHI_ERANGE, "atoms per site must be in 1..32");
+      maxa = std::max(maxa, na);
+      maxf = std::max(maxf, nf);
+      for (int i = 0; i < na; ++i) {
+        const int at = sites->site_atoms[atom_off.back() + i];
+        if (at < 0 || at >= n_atoms) return bad(MAHI_EINVAL, "site atom index out of range");
+        if (used[at]) return bad(MAHI_EINVAL, "site atoms overlap");
+        used[at] = 1;
+        site_atoms.push_back(at);
+      }
+      fq_off.push_back((int)fo);
+      for (int k = 0; k < nf * na; ++k) {
+        const double v = sites->form_charges[fo + k];
+        if (!is_fin(v)) return bad(MAHI_EINVAL, "non-finite form charge");
+        fq.push_back(v);
+      }
+      fo += (int64_t)nf * na;
+      atom_off.push_back(atom_off.back() + na);
+      form_off.push_back(form_off.back() + nf);
+    }
+    for (size_t i = 0; i < site_atoms.size(); ++i) q_env[site_atoms[i]] = 0.0;
+  }
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) return bad(MAHI_EDEVICE, "no HIP device");
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return bad(MAHI_EDEVICE, "hipGetDevice failed");
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, dev) != hipSuccess) return bad(MAHI_EDEVICE, "hipGetDeviceProperties failed");
+  if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
+    return bad(MAHI_EDEVICE, std::string("built for gfx950, found ") + prop.gcnArchName);
+  mahi_ctx *ctx = new (std::nothrow) mahi_ctx;
+  if (!ctx) return bad(MAHI_ENOMEM, "host allocation failed");
+  ctx->N = n_atoms;
+  ctx->periodic = box->periodic;
+  ctx->edge = box->edge;
+  ctx->p = opts->order;
+  ctx->d = opts->depth;
+  ctx->prec = opts->precision;
+  ctx->ke = opts->coulomb_k > 0 ? opts->coulomb_k : kDefaultKe;
+  ctx->device = dev;
+  ctx->M = M;
+  ctx->nforms = form_off.back();
+  ctx->nsite_atoms = (int)site_atoms.size();
+  ctx->maxa = maxa;
+  ctx->maxf = maxf;
+  ctx->lambda_set = (M == 0);
+  if (M > 0 && site_lds_bytes(ctx->p, maxa, maxf) + 24 * 1024 > (size_t)std::min<size_t>(prop.sharedMemPerBlock, 65536)) {
+    delete ctx;
+    return bad(MAHI_ERANGE, "order too high for the site correction's local memory with these site sizes");
+  }
+  if (opts->hip_stream) {
+    ctx->stream = static_cast<hipStream_t>(opts->hip_stream);
+  } else {
+    if (hipStreamCreateWithFlags(&ctx->stream, hipStreamNonBlocking) != hipSuccess) {
+      delete ctx;
+      return bad(MAHI_EDEVICE, "stream creation failed");
+    }
+    ctx->own_stream = true;
+  }
+  mahi_status s = ctx->prec == 32 ? setup_device<float>(ctx, q_env, atom_off, form_off, fq_off, site_atoms, fq)
+                                   : setup_device<double>(ctx, q_env, atom_off, form_off, fq_off, site_atoms, fq);
+  if (s != MAHI_OK) {
+    g_create_error = ctx->err;
+    free_ctx(ctx);
+    return s;
+  }
+  *out = ctx;
+  return MAHI_OK;
+}
+
+mahi_status mahi_set_lambda(mahi_ctx *ctx, const double *lt) {
+  if (!ctx) return MAHI_EINVAL;
+  if (ctx->M == 0) {
+    ctx->lambda_set = true;
+    return MAHI_OK;
+  }
+  if (!lt) return ctx->fail(MAHI_EINVAL, "lambda_tilde is NULL");
+  for (int i = 0; i < ctx->nforms; ++i)
+    if (!is_fin(lt[i])) return ctx->fail(MAHI_EINVAL, "non-finite lambda_tilde");
+  HIP_TRY(hipSetDevice(ctx->device), "set device");
+  HIP_TRY(hipMemcpyAsync(ctx->lam, lt, sizeof(double) * ctx->nforms, hipMemcpyHostToDevice, ctx->stream), "copy lambda");
+  if (ctx->prec == 32) {
+    SiteArgs s = site_args<float>(ctx);
+    launch_charge_scale<float>(s, ctx->lam, static_cast<float *>(ctx->qt), ctx->stream);
+  } else {
+    SiteArgs s = site_args<double>(ctx);
+    launch_charge_scale<double>(s, ctx->lam, static_cast<double *>(ctx->qt), ctx->stream);
+  }
+  HIP_TRY(hipGetLastError(), "charge scaling launch");
+  HIP_TRY(hipStreamSynchronize(ctx->stream), "charge scaling");
+  ctx->lambda_set = true;
+  return MAHI_OK;
+}
+
+mahi_status mahi_eval(mahi_ctx *ctx, const mahi_eval_args *a) {
+  if (!ctx) return MAHI_EINVAL;
+  if (!a || !a->xyz) return ctx->fail(MAHI_EINVAL, "args and args->xyz must not be NULL");
+  if (a->flags & ~MAHI_DEVICE_IO) return ctx->fail(MAHI_EINVAL, "unknown flags");
+  if (!ctx->lambda_set) return ctx->fail(MAHI_ESTATE, "mahi_set_lambda must be called before mahi_eval");
+  if (!(a->flags & MAHI_DEVICE_IO)) {
+    const int64_t n3 = 3 * ctx->N;
+    if (ctx->prec == 32) {
+      const float *x = static_cast<const float *>(a->xyz);
+      for (int64_t i = 0; i < n3; ++i)
+        if (!std::isfinite(x[i])) return ctx->fail(MAHI_EINVAL, "non-finite coordinate");
+    } else {
+      const double *x = static_cast<const double *>(a->xyz);
+      for (int64_t i = 0; i < n3; ++i)
+        if (!std::isfinite(x[i])) return ctx->fail(MAHI_EINVAL, "non-finite coordinate");
+    }
+  }
+  return ctx->prec == 32 ? eval_impl<float>(ctx, a) : eval_impl<double>(ctx, a);
+}
+
+void mahi_destroy(mahi_ctx *ctx) { free_ctx(ctx); }
+
+mahi_status mahi_info(const mahi_ctx *ctx, int64_t *n_atoms, int32_t *n_sites, int32_t *n_forms, int *order, int *depth,
+                      int *precision) {
+  if (!ctx) return MAHI_EINVAL;
+  if (n_atoms) *n_atoms = ctx->N;
+  if (n_sites) *n_sites = ctx->M;
+  if (n_forms) *n_forms = ctx->nforms;
+  if (order) *order = ctx->p;
+  if (depth) *depth = ctx->d;
+  if (precision) *precision = ctx->prec;
+  return MAHI_OK;
+}
+
+const char *mahi_stage_name(int stage) {
+  static const char *names[MAHI_N_STAGES] = {"tree", "p2m", "m2m", "lattice", "m2l", "l2l", "p2p_l2p", "site", "energy"};
+  return (stage >= 0 && stage < MAHI_N_STAGES) ? names[stage] : "unknown";
+}
+
+mahi_status mahi_profile_begin(mahi_ctx *ctx, int max_evals) {
+  if (!ctx) return MAHI_EINVAL;
+  if (max_evals < 1 || max_evals > 100000) return ctx->fail(MAHI_ERANGE, "max_evals must be in 1..100000");
+  HIP_TRY(hipSetDevice(ctx->device), "set device");
+  HIP_TRY(hipStreamSynchronize(ctx->stream), "synchronise");
+  for (auto &e : ctx->prof_events) (void)hipEventDestroy(e);
+  ctx->prof_events.assign((size_t)max_evals * (MAHI_N_STAGES + 1), nullptr);
+  for (auto &e : ctx->prof_events) HIP_TRY(hipEventCreate(&e), "event create");
+  ctx->prof_max = max_evals;
+  ctx->prof_n = 0;
+  return MAHI_OK;
+}
+
+mahi_status mahi_profile_end(mahi_ctx *ctx, double *stage_ms, int *n_evals) {
+  if (!ctx || !stage_ms) return MAHI_EINVAL;
+  HIP_TRY(hipSetDevice(ctx->device), "set device");
+  HIP_TRY(hipStreamSynchronize(ctx->stream), "synchronise");
+  for (int s = 0; s < MAHI_N_STAGES; ++s) stage_ms[s] = 0.0;
+  for (int e = 0; e < ctx->prof_n; ++e)
+    for (int s = 0; s < MAHI_N_STAGES; ++s) {
+      float ms = 0.f;
+      HIP_TRY(hipEventElapsedTime(&ms, ctx->prof_events[(size_t)e * (MAHI_N_STAGES + 1) + s],
+                                  ctx->prof_events[(size_t)e * (MAHI_N_STAGES + 1) + s + 1]),
+              "event timing");
+      stage_ms[s] += ms;
+    }
+  if (ctx->prof_n > 0)
+    for (int s = 0; s < MAHI_N_STAGES; ++s) stage_ms[s] /= ctx->prof_n;
+  if (n_evals) *n_evals = ctx->prof_n;
+  for (auto &e : ctx->prof_events) (void)hipEventDestroy(e);
+  ctx->prof_events.clear();
+  ctx->prof_max = ctx->prof_n = 0;
+  return MAHI_OK;
+}
+
+mahi_status mahi_debug_copy(mahi_ctx *ctx, int which, void *host_out, int64_t count) {
+  if (!ctx || !host_out || count < 0) return MAHI_EINVAL;
+  const size_t el = ctx->prec == 32 ? sizeof(float) : sizeof(double);
+  const int K = ncoef(ctx->p);
+  const int64_t nbox = level_offset(ctx->d + 1);
+  const void *src = nullptr;
+  size_t bytes = 0;
+  switch (which) {
+    case 0: src = ctx->Mc; bytes = el * nbox * K; break;
+    case 1: src = ctx->Lc; bytes = el * nbox * K; break;
+    case 2: src = ctx->start; bytes = sizeof(int) * ((size_t(1) << (3 * ctx->d)) + 1); break;
+    case 3: src = ctx->perm; bytes = sizeof(int) * ctx->N; break;
+    case 4: src = ctx->sorted; bytes = 4 * el * ctx->N; break;
+    default: return ctx->fail(MAHI_EINVAL, "unknown buffer");
+  }
+  const size_t want = (which == 2 || which == 3 ? sizeof(int) : el) * (size_t)count;
+  if (want > bytes) return ctx->fail(MAHI_ERANGE, "count exceeds the buffer");
+  HIP_TRY(hipSetDevice(ctx->device), "set device");
+  HIP_TRY(hipStreamSynchronize(ctx->stream), "synchronise");
+  HIP_TRY(hipMemcpy(host_out, src, want, hipMemcpyDeviceToHost), "copy");
+  return MAHI_OK;
+}
+
+mahi_status mahi_host_selftest(int order, double *max_rel_err) {
+  if (!max_rel_err) return MAHI_EINVAL;
+  if (order < 1 || order > kMaxOrder) return MAHI_ERANGE;
+  *max_rel_err = host_selftest(order);
+  return MAHI_OK;
+}
+
+mahi_status mahi_device_selftest(int precision, double *max_rel_err) {
+  if (!max_rel_err || (precision != 32 && precision != 64)) return MAHI_EINVAL;
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) return MAHI_EDEVICE;
+  const int rows = precision == 32 ? 96 : 48, kk = 84;
+  std::mt19937_64 rng(5);
+  std::uniform_real_distribution<double> U(-1.0, 1.0);
+  std::vector<double> A((size_t)kk * rows), B((size_t)kk * 64), C((size_t)rows * 64, 0.0);
+  for (auto &v : A) v = U(rng);
+  for (auto &v : B) v = U(rng);
+  for (int r = 0; r < rows; ++r)
+    for (int c = 0; c < 64; ++c)
+      for (int k = 0; k < kk; ++k) C[(size_t)r * 64 + c] += A[(size_t)k * rows + r] * B[(size_t)k * 64 + c];
+  auto run = [&](auto zero) -> mahi_status {
+    using T = decltype(zero);
+    std::vector<T> a(A.begin(), A.end()), b(B.begin(), B.end()), c((size_t)rows * 64);
+    T *da = nullptr, *db = nullptr, *dc = nullptr;
+    if (hipMalloc(&da, sizeof(T) * a.size()) != hipSuccess || hipMalloc(&db, sizeof(T) * b.size()) != hipSuccess ||
+        hipMalloc(&dc, sizeof(T) * c.size()) != hipSuccess)
+      return MAHI_ENOMEM;
+    (void)hipMemcpy(da, a.data(), sizeof(T) * a.size(), hipMemcpyHostToDevice);
+    (void)hipMemcpy(db, b.data(), sizeof(T) * b.size(), hipMemcpyHostToDevice);
+    launch_mfma_probe<T>(da, db, dc, rows, kk, nullptr);
+    hipError_t e = hipDeviceSynchronize();
+    (void)hipMemcpy(c.data(), dc, sizeof(T) * c.size(), hipMemcpyDeviceToHost);
+    (void)hipFree(da);
+    (void)hipFree(db);
+    (void)hipFree(dc);
+    if (e != hipSuccess) return MAHI_EDEVICE;
+    double worst = 0.0, nrm = 0.0;
+    for (size_t i = 0; i < c.size(); ++i) {
+      worst = std::max(worst, std::fabs((double)c[i] - C[i]));
+      nrm = std::max(nrm, std::fabs(C[i]));
+    }
+    *max_rel_err = worst / nrm;
+    return MAHI_OK;
+  };
+  return precision == 32 ? run(0.0f) : run(0.0);
+}
+
+}  // extern "C"

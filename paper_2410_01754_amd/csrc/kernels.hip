@@ -1,0 +1,1279 @@
+// gfx950 kernels of the MAHI hot path.
+//
+// One evaluation runs, in order (paper, section "Fast Multipole Method" and
+// Fig. fmm_scheme; section "Multipole-Accelerated Hamiltonian Interpolation"):
+//   bbox (open boundaries) -> bin -> scan -> scatter -> leaf sort/pack      octree build
+//   p2m -> m2m (levels d-1..0) -> lattice                                  upward pass, periodic images
+//   m2l (all levels, matrix cores) -> l2l (levels 1..d)                    far field
+//   p2p_l2p (near field + far field at the atoms + outputs)                 eq scaled_electrostatics
+//   site (per-site correction in float64) -> finalize (energy)             eqs correction_scheme..C_B
+// Positions inside the FMM are leaf-local (units of the leaf edge), so the
+// float32 path never subtracts large absolute coordinates.
+#include <hip/hip_runtime.h>
+
+#include "device_common.hpp"
+#include "kernels.hpp"
+
+namespace mahi {
+
+// ---------------------------------------------------------------------------
+// Recurrence constants of the Schmidt-normalised solid harmonics
+// ---------------------------------------------------------------------------
+__constant__ double c_sect[kMaxOrder + 2];                   // sqrt((2m-1)/(2m))
+__constant__ double c_up[kMaxOrder + 2];                     // sqrt(2m+1)
+__constant__ double c_b1[kMaxOrder + 1][kMaxOrder + 1];      // (2n-1)/sqrt(n^2-m^2)
+__constant__ double c_b2[kMaxOrder + 1][kMaxOrder + 1];      // sqrt((n-1)^2-m^2)/sqrt(n^2-m^2)
+__constant__ double c_dz[kMaxOrder + 1][kMaxOrder + 1];      // sqrt((j+1+b)(j+1-b))
+__constant__ double c_r1[kMaxOrder + 1][kMaxOrder + 1];      // sqrt((j+2-b)(j+1-b))
+__constant__ double c_r2[kMaxOrder + 1][kMaxOrder + 1];      // sqrt((j+b+2)(j+b+1))
+
+hipError_t upload_constants() {
+  double sect[kMaxOrder + 2], up[kMaxOrder + 2];
+  static double b1[kMaxOrder + 1][kMaxOrder + 1], b2[kMaxOrder + 1][kMaxOrder + 1];
+  static double dz[kMaxOrder + 1][kMaxOrder + 1], r1[kMaxOrder + 1][kMaxOrder + 1], r2[kMaxOrder + 1][kMaxOrder + 1];
+  for (int m = 0; m < kMaxOrder + 2; ++m) {
+    sect[m] = m > 0 ? sqrt((2.0 * m - 1.0) / (2.0 * m)) : 0.0;
+    up[m] = sqrt(2.0 * m + 1.0);
+  }
+  for (int n = 0; n <= kMaxOrder; ++n)
+    for (int m = 0; m <= kMaxOrder; ++m) {
+      const double den = double(n * n - m * m);
+      b1[n][m] = (m <= n - 2) ? (2.0 * n - 1.0) / sqrt(den) : 0.0;
+      b2[n][m] = (m <= n - 2) ? sqrt(double((n - 1) * (n - 1) - m * m)) / sqrt(den) : 0.0;
+      dz[n][m] = (m <= n) ? sqrt(double((n + 1 + m) * (n + 1 - m))) : 0.0;
+      r1[n][m] = (m <= n) ? sqrt(double((n + 2 - m) * (n + 1 - m))) : 0.0;
+      r2[n][m] = (m <= n) ? sqrt(double((n + m + 2) * (n + m + 1))) : 0.0;
+    }
+  hipError_t e;
+  if ((e = hipMemcpyToSymbol(HIP_SYMBOL(c_sect), sect, sizeof(sect))) != hipSuccess) return e;
+  if ((e = hipMemcpyToSymbol(HIP_SYMBOL(c_up), up, sizeof(up))) != hipSuccess) return e;
+  if ((e = hipMemcpyToSymbol(HIP_SYMBOL(c_b1), b1, sizeof(b1))) != hipSuccess) return e;
+  if ((e = hipMemcpyToSymbol(HIP_SYMBOL(c_b2), b2, sizeof(b2))) != hipSuccess) return e;
+  if ((e = hipMemcpyToSymbol(HIP_SYMBOL(c_dz), dz, sizeof(dz))) != hipSuccess) return e;
+  if ((e = hipMemcpyToSymbol(HIP_SYMBOL(c_r1), r1, sizeof(r1))) != hipSuccess) return e;
+  return hipMemcpyToSymbol(HIP_SYMBOL(c_r2), r2, sizeof(r2));
+}
+
+__host__ __device__ inline int ridx_d(int n, int m, int im) { return m == 0 ? n * n : n * n + 2 * m - 1 + im; }
+
+// Visit Rt_n^m(x, y, z) for 0 <= m <= n <= p, m-major, with O(1) registers.
+template <class T, class F>
+__device__ __forceinline__ void for_regular(int p, T x, T y, T z, F &&f) {
+  const T r2 = x * x + y * y + z * z;
+  T sr = T(1), si = T(0);
+  for (int m = 0; m <= p; ++m) {
+    if (m > 0) {
+      const T c = -(T)c_sect[m];
+      const T nr = c * (x * sr - y * si);
+      const T ni = c * (x * si + y * sr);
+      sr = nr;
+      si = ni;
+    }
+    f(m, m, sr, si);
+    if (m == p) break;
+    T r1r = (T)c_up[m] * z * sr, r1i = (T)c_up[m] * z * si;
+    f(m + 1, m, r1r, r1i);
+    T r0r = sr, r0i = si;
+    for (int n = m + 2; n <= p; ++n) {
+      const T b1 = (T)c_b1[n][m], b2 = (T)c_b2[n][m];
+      const T nr = b1 * z * r1r - b2 * r2 * r0r;
+      const T ni = b1 * z * r1i - b2 * r2 * r0i;
+      r0r = r1r;
+      r0i = r1i;
+      r1r = nr;
+      r1i = ni;
+      f(n, m, nr, ni);
+    }
+  }
+}
+
+// Derivative local coefficients: for phi = sum L conj(Rt(u)), d phi / du_{x,y,z}
+// = sum D_{x,y,z} conj(Rt(u)) over degrees j < p, with each D_j^b formed from
+// L_{j+1}^{b-1}, L_{j+1}^b, L_{j+1}^{b+1} (gradient relations of the solid
+// harmonics).  L is real-packed; returns (Re, Im) of D_x, D_y, D_z at (j, b).
+template <class T>
+__device__ __forceinline__ void grad_coeffs(const T *L, int j, int b, T &xr, T &xi, T &yr, T &yi, T &zr, T &zi) {
+  const int n = j + 1;
+  const T br = L[ridx_d(n, b, 0)], bi = b ? L[ridx_d(n, b, 1)] : T(0);
+  T ar, ai;
+  if (b >= 2) {
+    ar = L[ridx_d(n, b - 1, 0)];
+    ai = L[ridx_d(n, b - 1, 1)];
+  } else if (b == 1) {
+    ar = L[ridx_d(n, 0, 0)];
+    ai = T(0);
+  } else {  // L^{-1} = -conj(L^1)
+    ar = -L[ridx_d(n, 1, 0)];
+    ai = L[ridx_d(n, 1, 1)];
+  }
+  const T cr = L[ridx_d(n, b + 1, 0)], ci = L[ridx_d(n, b + 1, 1)];
+  const T dz = (T)c_dz[j][b], r1 = (T)c_r1[j][b], r2 = (T)c_r2[j][b];
+  zr = dz * br;
+  zi = dz * bi;
+  xr = T(0.5) * (r1 * ar - r2 * cr);
+  xi = T(0.5) * (r1 * ai - r2 * ci);
+  yr = T(-0.5) * (r2 * ci + r1 * ai);
+  yi = T(0.5) * (r2 * cr + r1 * ar);
+}
+
+template <class T>
+__device__ __forceinline__ T rsqrt_t(T x);
+template <>
+__device__ __forceinline__ float rsqrt_t<float>(float x) {
+  return __builtin_amdgcn_rsqf(x);
+}
+template <>
+__device__ __forceinline__ double rsqrt_t<double>(double x) {
+  return 1.0 / sqrt(x);
+}
+
+// ---------------------------------------------------------------------------
+// Small utility kernels
+// ---------------------------------------------------------------------------
+__global__ void k_fill_i32(int *p, int v, int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) p[i] = v;
+}
+
+template <class T>
+__global__ void k_bbox_partial(const T *__restrict__ xyz, int64_t n, double *__restrict__ part) {
+  __shared__ double s[6][256];
+  double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300};
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    for (int d = 0; d < 3; ++d) {
+      const double v = (double)xyz[3 * i + d];
+      lo[d] = fmin(lo[d], v);
+      hi[d] = fmax(hi[d], v);
+    }
+  for (int d = 0; d < 3; ++d) {
+    s[d][threadIdx.x] = lo[d];
+    s[3 + d][threadIdx.x] = hi[d];
+  }
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w)
+      for (int d = 0; d < 3; ++d) {
+        s[d][threadIdx.x] = fmin(s[d][threadIdx.x], s[d][threadIdx.x + w]);
+        s[3 + d][threadIdx.x] = fmax(s[3 + d][threadIdx.x], s[3 + d][threadIdx.x + w]);
+      }
+    __syncthreads();
+  }
+  if (threadIdx.x < 6) part[blockIdx.x * 6 + threadIdx.x] = s[threadIdx.x][0];
+}
+
+__global__ void k_bbox_final(const double *__restrict__ part, int nblk, Geom *g) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300};
+  for (int b = 0; b < nblk; ++b)
+    for (int d = 0; d < 3; ++d) {
+      lo[d] = fmin(lo[d], part[b * 6 + d]);
+      hi[d] = fmax(hi[d], part[b * 6 + 3 + d]);
+    }
+  double ext = fmax(fmax(hi[0] - lo[0], hi[1] - lo[1]), hi[2] - lo[2]);
+  double edge = ext * (1.0 + 1e-6) + 1e-9;
+  for (int d = 0; d < 3; ++d) g->origin[d] = lo[d] - 0.5 * (edge - (hi[d] - lo[d]));
+  g->edge = edge;
+}
+
+// ---------------------------------------------------------------------------
+// Octree build: counting sort of atoms by Morton leaf index
+// ---------------------------------------------------------------------------
+template <class T>
+__device__ __forceinline__ void locate(const T *xyz, int64_t i, const Geom &g, int periodic, int n, double w[3], int c[3]) {
+  const double h = g.edge / n;
+  for (int d = 0; d < 3; ++d) {
+    const double x = (double)xyz[3 * i + d];
+    w[d] = periodic ? wrap_coord(x, g.edge) : x - g.origin[d];
+    int ci = (int)floor(w[d] / h);
+    c[d] = ci < 0 ? 0 : (ci >= n ? n - 1 : ci);
+  }
+}
+
+template <class T>
+__global__ void k_bin(const T *__restrict__ xyz, int64_t n_atoms, const Geom *__restrict__ gp, int d, int periodic,
+                      int *__restrict__ key, int *__restrict__ count) {
+  const Geom g = *gp;
+  const int n = 1 << d;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n_atoms; i += (int64_t)gridDim.x * blockDim.x) {
+    double w[3];
+    int c[3];
+    locate(xyz, i, g, periodic, n, w, c);
+    const int k = (int)morton(c[0], c[1], c[2]);
+    key[i] = k;
+    atomicAdd(&count[k], 1);
+  }
+}
+
+// Exclusive scan of leaf counts (one block of 1024 threads); also seeds the scatter cursors.
+__global__ void __launch_bounds__(1024) k_scan(const int *__restrict__ count, int *__restrict__ start,
+                                               int *__restrict__ cursor, int nleaf) {
+  __shared__ int part[1024];
+  const int t = threadIdx.x;
+  const int per = (nleaf + 1023) / 1024;
+  const int b = t * per, e = min(nleaf, b + per);
+  int s = 0;
+  for (int i = b; i < e; ++i) s += count[i];
+  part[t] = s;
+  __syncthreads();
+  for (int off = 1; off < 1024; off <<= 1) {
+    int v = (t >= off) ? part[t - off] : 0;
+    __syncthreads();
+    part[t] += v;
+    __syncthreads();
+  }
+  int run = part[t] - s;
+  for (int i = b; i < e; ++i) {
+    start[i] = run;
+    cursor[i] = run;
+    run += count[i];
+  }
+  if (t == 1023) start[nleaf] = part[1023];
+}
+
+__global__ void k_scatter(const int *__restrict__ key, int *__restrict__ cursor, int *__restrict__ tmp, int64_t n_atoms) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n_atoms; i += (int64_t)gridDim.x * blockDim.x) {
+    const int slot = atomicAdd(&cursor[key[i]], 1);
+    tmp[slot] = (int)i;
+  }
+}
+
+// One wave per leaf: order the leaf's atoms by original index (deterministic
+// layout), then write the permutation, its inverse and the packed leaf-local
+// coordinates with scaled charges.
+template <class T>
+__global__ void __launch_bounds__(256) k_leafsort(const int *__restrict__ tmp, const int *__restrict__ start, int nleaf,
+                                                  const T *__restrict__ xyz, const T *__restrict__ qt,
+                                                  const Geom *__restrict__ gp, int d, int periodic,
+                                                  int *__restrict__ perm, int *__restrict__ slot_of,
+                                                  Atom4<T> *__restrict__ sorted) {
+  const int leaf = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (leaf >= nleaf) return;
+  const Geom g = *gp;
+  const int n = 1 << d;
+  const double h = g.edge / n;
+  const int s0 = start[leaf], cnt = start[leaf + 1] - s0;
+  for (int a = lane; a < cnt; a += 64) {
+    const int me = tmp[s0 + a];
+    int rank = 0;
+    for (int b = 0; b < cnt; ++b) rank += (tmp[s0 + b] < me) ? 1 : 0;
+    const int slot = s0 + rank;
+    perm[slot] = me;
+    slot_of[me] = slot;
+    double w[3];
+    int c[3];
+    locate(xyz, me, g, periodic, n, w, c);
+    Atom4<T> at;
+    at.x = (T)(w[0] / h - (c[0] + 0.5));
+    at.y = (T)(w[1] / h - (c[1] + 0.5));
+    at.z = (T)(w[2] / h - (c[2] + 0.5));
+    at.q = qt[me];
+    sorted[slot] = at;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// P2M: leaf multipoles; also the float64 charge moments for the lattice
+// ---------------------------------------------------------------------------
+template <class T>
+__global__ void __launch_bounds__(64) k_p2m(const Atom4<T> *__restrict__ sorted, const int *__restrict__ start,
+                                            int p, int K, int chunk, T *__restrict__ Mleaf, double *__restrict__ qds,
+                                            const Geom *__restrict__ gp, int d) {
+  extern __shared__ unsigned char smem_raw[];
+  T *rows = reinterpret_cast<T *>(smem_raw);
+  const int leaf = blockIdx.x, lane = threadIdx.x;
+  const int s0 = start[leaf], cnt = start[leaf + 1] - s0;
+  constexpr int kMaxPer = ((kMaxOrder + 1) * (kMaxOrder + 1) + 63) / 64;
+  T acc[kMaxPer];
+#pragma unroll
+  for (int i = 0; i < kMaxPer; ++i) acc[i] = T(0);
+  for (int c0 = 0; c0 < cnt; c0 += chunk) {
+    const int nch = min(chunk, cnt - c0);
+    if (lane < nch) {
+      const Atom4<T> a = sorted[s0 + c0 + lane];
+      T *row = rows + lane * K;
+      for_regular(p, a.x, a.y, a.z, [&](int n, int m, T re, T im) {
+        const int i0 = ridx_d(n, m, 0);
+        row[i0] = a.q * re;
+        if (m) row[i0 + 1] = -a.q * im;
+      });
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < kMaxPer; ++i) {
+      const int k = lane + 64 * i;
+      if (k < K)
+        for (int r = 0; r < nch; ++r) acc[i] += rows[r * K + k];
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int i = 0; i < kMaxPer; ++i) {
+    const int k = lane + 64 * i;
+    if (k < K) Mleaf[(int64_t)leaf * K + k] = acc[i];
+  }
+  if (qds) {
+    const Geom g = *gp;
+    const int n = 1 << d;
+    const double h = g.edge / n, half = 0.5 * g.edge;
+    int cx, cy, cz;
+    unmorton((uint32_t)leaf, cx, cy, cz);
+    double v[5] = {0, 0, 0, 0, 0};
+    for (int t = lane; t < cnt; t += 64) {
+      const Atom4<T> a = sorted[s0 + t];
+      const double ax = (cx + 0.5 + (double)a.x) * h - half;
+      const double ay = (cy + 0.5 + (double)a.y) * h - half;
+      const double az = (cz + 0.5 + (double)a.z) * h - half;
+      const double q = (double)a.q;
+      v[0] += q;
+      v[1] += q * ax;
+      v[2] += q * ay;
+      v[3] += q * az;
+      v[4] += q * (ax * ax + ay * ay + az * az);
+    }
+    for (int off = 32; off > 0; off >>= 1)
+      for (int k = 0; k < 5; ++k) v[k] += __shfl_xor(v[k], off);
+    if (lane == 0)
+      for (int k = 0; k < 5; ++k) qds[(int64_t)leaf * 5 + k] = v[k];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// M2M and L2L: dense per-child translations, PB parents per block
+// ---------------------------------------------------------------------------
+template <class T>
+__global__ void __launch_bounds__(128) k_m2m(T *__restrict__ M, int lp, int K, const T *__restrict__ Tm, int PB) {
+  extern __shared__ unsigned char smem_raw[];
+  T *ch = reinterpret_cast<T *>(smem_raw);  // [PB][8][K]
+  const int64_t nparent = int64_t(1) << (3 * lp);
+  const int64_t p0 = (int64_t)blockIdx.x * PB;
+  const int64_t offc = level_offset(lp + 1) * K, offp = level_offset(lp) * K;  // element offsets
+  for (int e = threadIdx.x; e < PB * 8 * K; e += blockDim.x) {
+    const int pb = e / (8 * K), rem = e % (8 * K);
+    const int64_t P = p0 + pb;
+    ch[e] = (P < nparent) ? M[offc + 8 * P * K + rem] : T(0);
+  }
+  __syncthreads();
+  for (int r = threadIdx.x; r < K; r += blockDim.x) {
+    T acc[8];
+#pragma unroll
+    for (int pb = 0; pb < 8; ++pb) acc[pb] = T(0);
+    for (int s = 0; s < 8; ++s)
+      for (int c = 0; c < K; ++c) {
+        const T t = Tm[((int64_t)s * K + c) * K + r];
+#pragma unroll
+        for (int pb = 0; pb < 8; ++pb)
+          if (pb < PB) acc[pb] += t * ch[(pb * 8 + s) * K + c];
+      }
+#pragma unroll
+    for (int pb = 0; pb < 8; ++pb)
+      if (pb < PB && p0 + pb < nparent) M[offp + (p0 + pb) * K + r] = acc[pb];
+  }
+}
+
+template <class T>
+__global__ void __launch_bounds__(128) k_l2l(T *__restrict__ L, int lc, int K, const T *__restrict__ Tl, int PB) {
+  extern __shared__ unsigned char smem_raw[];
+  T *par = reinterpret_cast<T *>(smem_raw);  // [PB][K]
+  const int64_t nparent = int64_t(1) << (3 * (lc - 1));
+  const int64_t p0 = (int64_t)blockIdx.x * PB;
+  const int64_t offc = level_offset(lc) * K, offp = level_offset(lc - 1) * K;  // element offsets
+  for (int e = threadIdx.x; e < PB * K; e += blockDim.x) {
+    const int pb = e / K, c = e % K;
+    par[e] = (p0 + pb < nparent) ? L[offp + (p0 + pb) * K + c] : T(0);
+  }
+  __syncthreads();
+  for (int r = threadIdx.x; r < K; r += blockDim.x) {
+    for (int s = 0; s < 8; ++s) {
+      T acc[8];
+#pragma unroll
+      for (int pb = 0; pb < 8; ++pb) acc[pb] = T(0);
+      for (int c = 0; c < K; ++c) {
+        const T t = Tl[((int64_t)s * K + c) * K + r];
+#pragma unroll
+        for (int pb = 0; pb < 8; ++pb)
+          if (pb < PB) acc[pb] += t * par[pb * K + c];
+      }
+#pragma unroll
+      for (int pb = 0; pb < 8; ++pb)
+        if (pb < PB && p0 + pb < nparent) L[offc + (8 * (p0 + pb) + s) * K + r] += acc[pb];
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Periodic lattice: root local from the root multipole (float64), plus the
+// float64 charge moments Q, D, S2 of the r^2 part of the lattice remainder.
+// ---------------------------------------------------------------------------
+template <class T>
+__global__ void __launch_bounds__(256) k_lattice(const T *__restrict__ M, T *__restrict__ L,
+                                                 const double *__restrict__ LamT, int K,
+                                                 const double *__restrict__ qds, int nleaf, Geom *g) {
+  __shared__ double red[5][256];
+  __shared__ double mroot[(kMaxOrder + 1) * (kMaxOrder + 1)];
+  const int t = threadIdx.x;
+  double v[5] = {0, 0, 0, 0, 0};
+  for (int l = t; l < nleaf; l += 256)
+    for (int k = 0; k < 5; ++k) v[k] += qds[(int64_t)l * 5 + k];
+  for (int k = 0; k < 5; ++k) red[k][t] = v[k];
+  for (int c = t; c < K; c += 256) mroot[c] = (double)M[c];
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (t < w)
+      for (int k = 0; k < 5; ++k) red[k][t] += red[k][t + w];
+    __syncthreads();
+  }
+  if (t == 0) {
+    g->Q = red[0][0];
+    g->D[0] = red[1][0];
+    g->D[1] = red[2][0];
+    g->D[2] = red[3][0];
+    g->S2 = red[4][0];
+  }
+  for (int r = t; r < K; r += 256) {
+    double acc = 0.0;
+    for (int c = 0; c < K; ++c) acc += LamT[(int64_t)c * K + r] * mroot[c];
+    L[r] = (T)acc;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// M2L on the matrix cores.
+// For a level, a parity class c (position of the target inside its parent)
+// has one fixed list of 189 source offsets v.  A block takes 64 targets of one
+// class (children c of 64 consecutive parents) and one group of 32-row (f32) or
+// 16-row (f64) output tiles; for every v it stages the 64 gathered source
+// multipoles in LDS (B operand, K x 64) and multiplies with the dense operator
+// T_v (A operand, rows x K, read from the table in L2) on MFMA tiles:
+//   L_t (rows x 64) += T_v (rows x K) * [M_{t-v}] (K x 64).
+// ---------------------------------------------------------------------------
+typedef float floatx16 __attribute__((ext_vector_type(16)));
+typedef double doublex4 __attribute__((ext_vector_type(4)));
+
+template <class T>
+struct Mfma;
+template <>
+struct Mfma<float> {
+  static constexpr int TM = 32, TN = 32, TK = 2, NACC = 16;
+  using acc_t = floatx16;
+  __device__ static acc_t mma(float a, float b, acc_t c) { return __builtin_amdgcn_mfma_f32_32x32x2f32(a, b, c, 0, 0, 0); }
+  __device__ static int a_row(int l) { return l & 31; }
+  __device__ static int a_k(int l) { return l >> 5; }
+  __device__ static int b_k(int l) { return l >> 5; }
+  __device__ static int b_col(int l) { return l & 31; }
+  __device__ static int d_row(int l, int r) { return 8 * (r >> 2) + 4 * (l >> 5) + (r & 3); }
+  __device__ static int d_col(int l, int) { return l & 31; }
+};
+template <>
+struct Mfma<double> {
+  static constexpr int TM = 16, TN = 16, TK = 4, NACC = 4;
+  using acc_t = doublex4;
+  __device__ static acc_t mma(double a, double b, acc_t c) { return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0); }
+  __device__ static int a_row(int l) { return l & 15; }
+  __device__ static int a_k(int l) { return l >> 4; }
+  __device__ static int b_k(int l) { return l >> 4; }
+  __device__ static int b_col(int l) { return l & 15; }
+  __device__ static int d_row(int l, int r) { return 4 * r + (l >> 4); }
+  __device__ static int d_col(int l, int) { return l & 15; }
+};
+
+constexpr int kBStride = 65;  // LDS row stride of the staged B operand (64 targets + 1 pad)
+
+template <class T>
+__global__ void __launch_bounds__(256) k_m2l(const T *__restrict__ M, T *__restrict__ L, const T *__restrict__ Tab,
+                                             const int4 *__restrict__ lists, M2LArgs a) {
+  using MF = Mfma<T>;
+  constexpr int NCT = 64 / MF::TN;
+  extern __shared__ unsigned char smem_raw[];
+  T *Bs = reinterpret_cast<T *>(smem_raw);  // [kc][kBStride]
+  __shared__ int s_tx[64], s_ty[64], s_tz[64];
+  __shared__ int64_t s_src[64];
+
+  int item = blockIdx.x, l = a.lmin;
+  while (l < a.d && item >= a.level_start[l + 1]) ++l;
+  const int li = item - a.level_start[l];
+  const int64_t nparent = int64_t(1) << (3 * (l - 1));
+  const int chunks = (int)((nparent + 63) / 64);
+  const int g = li % a.ngroups;
+  const int tq = li / a.ngroups;
+  const int chunk = tq % chunks;
+  const int cls = tq / chunks;
+  const int nl = 1 << l;
+  const int64_t off = level_offset(l);  // box offset of level l
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int rt = g * a.nw + wave;
+  const bool active = rt < a.nrt;
+
+  if (threadIdx.x < 64) {
+    const int64_t P = (int64_t)chunk * 64 + threadIdx.x;
+    int tx = -1, ty = -1, tz = -1;
+    if (P < nparent) unmorton((uint32_t)(8 * P + cls), tx, ty, tz);
+    s_tx[threadIdx.x] = tx;
+    s_ty[threadIdx.x] = ty;
+    s_tz[threadIdx.x] = tz;
+  }
+
+  typename MF::acc_t acc[NCT];
+#pragma unroll
+  for (int c = 0; c < NCT; ++c)
+#pragma unroll
+    for (int r = 0; r < MF::NACC; ++r) acc[c][r] = T(0);
+
+  const int4 *lst = lists + cls * kListLen;
+  for (int vi = 0; vi < kListLen; ++vi) {
+    const int4 v = lst[vi];
+    __syncthreads();
+    if (threadIdx.x < 64) {
+      const int j = threadIdx.x;
+      int64_t src = -1;
+      if (s_tx[j] >= 0) {
+        int sx = s_tx[j] - v.x, sy = s_ty[j] - v.y, sz = s_tz[j] - v.z;
+        bool ok = true;
+        if (a.periodic) {
+          sx = (sx + 4 * nl) & (nl - 1);
+          sy = (sy + 4 * nl) & (nl - 1);
+          sz = (sz + 4 * nl) & (nl - 1);
+        } else {
+          ok = (unsigned)sx < (unsigned)nl && (unsigned)sy < (unsigned)nl && (unsigned)sz < (unsigned)nl;
+        }
+        if (ok) src = (off + (int64_t)morton(sx, sy, sz)) * a.K;
+      }
+      s_src[j] = src;
+    }
+    for (int k0 = 0; k0 < a.KK; k0 += a.kc) {
+      const int kn = min(a.kc, a.KK - k0);
+      __syncthreads();
+      for (int e = threadIdx.x; e < 64 * kn; e += blockDim.x) {
+        const int j = e / kn, kk = e - j * kn;
+        const int k = k0 + kk;
+        const int64_t src = s_src[j];
+        Bs[kk * kBStride + j] = (src >= 0 && k < a.K) ? M[src + k] : T(0);
+      }
+      __syncthreads();
+      if (active) {
+        const T *A = Tab + ((int64_t)v.w * a.KK + k0) * a.RP + rt * MF::TM;
+        for (int kb = 0; kb < kn; kb += MF::TK) {
+          const T af = A[(int64_t)(kb + MF::a_k(lane)) * a.RP + MF::a_row(lane)];
+#pragma unroll
+          for (int c = 0; c < NCT; ++c) {
+            const T bf = Bs[(kb + MF::b_k(lane)) * kBStride + c * MF::TN + MF::b_col(lane)];
+            acc[c] = MF::mma(af, bf, acc[c]);
+          }
+        }
+      }
+    }
+  }
+  if (active) {
+#pragma unroll
+    for (int c = 0; c < NCT; ++c)
+#pragma unroll
+      for (int r = 0; r < MF::NACC; ++r) {
+        const int row = rt * MF::TM + MF::d_row(lane, r);
+        const int col = c * MF::TN + MF::d_col(lane, r);
+        const int64_t P = (int64_t)chunk * 64 + col;
+        if (row < a.K && P < nparent) L[(off + 8 * P + cls) * a.K + row] = acc[c][r];
+      }
+  }
+}
+
+// Same contraction on the vector ALU (no matrix cores): accumulators of the
+// 64 targets live in LDS, each thread owns (target, row) pairs.  Used for
+// cross-checking the matrix-core path and as a fallback.
+template <class T>
+__global__ void __launch_bounds__(256) k_m2l_valu(const T *__restrict__ M, T *__restrict__ L,
+                                                  const T *__restrict__ Tab, const int4 *__restrict__ lists,
+                                                  M2LArgs a) {
+  extern __shared__ unsigned char smem_raw[];
+  T *Bs = reinterpret_cast<T *>(smem_raw);  // [K][64]
+  T *Acc = Bs + (size_t)a.K * 64;           // [64][K]
+  __shared__ int s_tx[64], s_ty[64], s_tz[64];
+  __shared__ int64_t s_src[64];
+  int item = blockIdx.x, l = a.lmin;
+  while (l < a.d && item >= a.level_start[l + 1]) ++l;
+  const int li = item - a.level_start[l];
+  const int64_t nparent = int64_t(1) << (3 * (l - 1));
+  const int chunks = (int)((nparent + 63) / 64);
+  const int chunk = li % chunks;
+  const int cls = li / chunks;
+  const int nl = 1 << l;
+  const int64_t off = level_offset(l);
+  const int K = a.K;
+  if (threadIdx.x < 64) {
+    const int64_t P = (int64_t)chunk * 64 + threadIdx.x;
+    int tx = -1, ty = -1, tz = -1;
+    if (P < nparent) unmorton((uint32_t)(8 * P + cls), tx, ty, tz);
+    s_tx[threadIdx.x] = tx;
+    s_ty[threadIdx.x] = ty;
+    s_tz[threadIdx.x] = tz;
+  }
+  for (int e = threadIdx.x; e < 64 * K; e += blockDim.x) Acc[e] = T(0);
+  const int4 *lst = lists + cls * kListLen;
+  for (int vi = 0; vi < kListLen; ++vi) {
+    const int4 v = lst[vi];
+    __syncthreads();
+    if (threadIdx.x < 64) {
+      const int j = threadIdx.x;
+      int64_t src = -1;
+      if (s_tx[j] >= 0) {
+        int sx = s_tx[j] - v.x, sy = s_ty[j] - v.y, sz = s_tz[j] - v.z;
+        bool ok = true;
+        if (a.periodic) {
+          sx = (sx + 4 * nl) & (nl - 1);
+          sy = (sy + 4 * nl) & (nl - 1);
+          sz = (sz + 4 * nl) & (nl - 1);
+        } else {
+          ok = (unsigned)sx < (unsigned)nl && (unsigned)sy < (unsigned)nl && (unsigned)sz < (unsigned)nl;
+        }
+        if (ok) src = (off + (int64_t)morton(sx, sy, sz)) * K;
+      }
+      s_src[j] = src;
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < 64 * K; e += blockDim.x) {
+      const int j = e / K, k = e - j * K;
+      const int64_t src = s_src[j];
+      Bs[k * 64 + j] = src >= 0 ? M[src + k] : T(0);
+    }
+    __syncthreads();
+    const T *A = Tab + (int64_t)v.w * a.KK * a.RP;
+    for (int e = threadIdx.x; e < 64 * K; e += blockDim.x) {
+      const int row = e / 64, j = e & 63;
+      T acc = Acc[j * K + row];
+      for (int k = 0; k < K; ++k) acc += A[(int64_t)k * a.RP + row] * Bs[k * 64 + j];
+      Acc[j * K + row] = acc;
+    }
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < 64 * K; e += blockDim.x) {
+    const int j = e / K, row = e - j * K;
+    const int64_t P = (int64_t)chunk * 64 + j;
+    if (P < nparent) L[(off + 8 * P + cls) * K + row] = Acc[e];
+  }
+}
+
+// Matrix-core tile check: C[rows x 64] = A[rows x kk] * B[kk x 64] with the same
+// fragment mapping as k_m2l (A given k-major as [kk][rows]).
+template <class T>
+__global__ void k_mfma_probe(const T *__restrict__ A, const T *__restrict__ B, T *__restrict__ C, int rows, int kk) {
+  using MF = Mfma<T>;
+  constexpr int NCT = 64 / MF::TN;
+  const int lane = threadIdx.x & 63;
+  const int rt = threadIdx.x >> 6;
+  typename MF::acc_t acc[NCT];
+#pragma unroll
+  for (int c = 0; c < NCT; ++c)
+#pragma unroll
+    for (int r = 0; r < MF::NACC; ++r) acc[c][r] = T(0);
+  for (int kb = 0; kb < kk; kb += MF::TK) {
+    const T af = A[(kb + MF::a_k(lane)) * rows + rt * MF::TM + MF::a_row(lane)];
+#pragma unroll
+    for (int c = 0; c < NCT; ++c) acc[c] = MF::mma(af, B[(kb + MF::b_k(lane)) * 64 + c * MF::TN + MF::b_col(lane)], acc[c]);
+  }
+#pragma unroll
+  for (int c = 0; c < NCT; ++c)
+#pragma unroll
+    for (int r = 0; r < MF::NACC; ++r)
+      C[(rt * MF::TM + MF::d_row(lane, r)) * 64 + c * MF::TN + MF::d_col(lane, r)] = acc[c][r];
+}
+
+// ---------------------------------------------------------------------------
+// Near field + far-field evaluation at the atoms + outputs.
+// A block owns the 2x2x2 leaves of one level d-1 box (the single leaf when
+// d = 0).  It stages the atoms of the surrounding 4x4x4 leaves (3x3x3 images
+// at d = 0) in LDS, in block-centred leaf units with each neighbour's periodic
+// image shift already applied, in chunks of at most `cap` atoms.  Each thread
+// owns one target atom: it sums q/r and q r/r^3 over its 27 neighbour leaves,
+// then evaluates its leaf's local expansion (potential and gradient), adds the
+// r^2 part of the lattice remainder, and writes the potential (sorted order),
+// the force (user order) and the block's float64 energy partial.
+// ---------------------------------------------------------------------------
+template <class T>
+__global__ void __launch_bounds__(256) k_p2p_l2p(const Atom4<T> *__restrict__ sorted, const int *__restrict__ start,
+                                                 const int *__restrict__ perm, const T *__restrict__ Lleaf,
+                                                 const Geom *__restrict__ gp, P2PArgs a, T *__restrict__ phi_sorted,
+                                                 T *__restrict__ F, T *__restrict__ pot_user,
+                                                 double *__restrict__ epart) {
+  extern __shared__ unsigned char smem_raw[];
+  Atom4<T> *src = reinterpret_cast<Atom4<T> *>(smem_raw);
+  T *loc = reinterpret_cast<T *>(src + a.cap);  // [BL][K] leaf local expansions
+  __shared__ int s_start[64], s_pre[65], t_start[9];
+  __shared__ double s_red[4];
+
+  const int tid = threadIdx.x;
+  const int n = 1 << a.d;
+  const int BW = n >= 2 ? 2 : 1, SW = BW + 2, BL = BW * BW * BW, NS = SW * SW * SW;
+  int bx = 0, by = 0, bz = 0;
+  if (a.d >= 1) unmorton(blockIdx.x, bx, by, bz);
+  const int b0x = bx * BW, b0y = by * BW, b0z = bz * BW;
+  const int leafbase = a.d >= 1 ? (int)blockIdx.x * 8 : 0;
+
+  if (tid < NS) {
+    const int sx = tid / (SW * SW), sy = (tid / SW) % SW, sz = tid % SW;
+    int cx = b0x - 1 + sx, cy = b0y - 1 + sy, cz = b0z - 1 + sz;
+    bool ok = true;
+    if (a.periodic) {
+      cx = (cx + n) % n;
+      cy = (cy + n) % n;
+      cz = (cz + n) % n;
+    } else {
+      ok = (unsigned)cx < (unsigned)n && (unsigned)cy < (unsigned)n && (unsigned)cz < (unsigned)n;
+    }
+    int st = 0, cnt = 0;
+    if (ok) {
+      const int leaf = (int)morton(cx, cy, cz);
+      st = start[leaf];
+      cnt = start[leaf + 1] - st;
+    }
+    s_start[tid] = st;
+    s_pre[tid + 1] = cnt;  // prefix formed below
+  }
+  if (tid < BL) t_start[tid] = start[leafbase + tid];
+  if (tid == 0) t_start[BL] = start[leafbase + BL];
+  for (int e = tid; e < BL * a.K; e += blockDim.x) loc[e] = Lleaf[(int64_t)leafbase * a.K + e];
+  __syncthreads();
+  if (tid == 0) {
+    s_pre[0] = 0;
+    for (int s = 0; s < NS; ++s) s_pre[s + 1] += s_pre[s];
+  }
+  __syncthreads();
+
+  const Geom g = *gp;
+  const double h = g.edge / n, inv_h = 1.0 / h, half = 0.5 * g.edge;
+  const double c_r2 = a.periodic ? 2.0 * 3.14159265358979323846 / (3.0 * g.edge * g.edge * g.edge) : 0.0;
+  const T cen0 = T(-0.5) - T(0.5) * BW;  // slot s has centre s + cen0 (block-centred leaf units)
+  const int tbeg = t_start[0], tend = t_start[BL];
+  const int total = s_pre[NS];
+  double esum = 0.0;
+
+  for (int t0 = tbeg; t0 < tend; t0 += blockDim.x) {
+    const int ti = t0 + tid;
+    const bool valid = ti < tend;
+    Atom4<T> me = {T(0), T(0), T(0), T(0)};
+    int my = 0;
+    if (valid) {
+      me = sorted[ti];
+      for (int b = 1; b < BL; ++b)
+        if (ti >= t_start[b]) my = b;
+    }
+    const int lx = BW == 2 ? (my >> 2) & 1 : 0, ly = BW == 2 ? (my >> 1) & 1 : 0, lz = BW == 2 ? my & 1 : 0;
+    const T px = me.x + (T)(lx + 1) + cen0, py = me.y + (T)(ly + 1) + cen0, pz = me.z + (T)(lz + 1) + cen0;
+    T phi = T(0), ex = T(0), ey = T(0), ez = T(0);
+    for (int c0 = 0; c0 < total; c0 += a.cap) {
+      const int c1 = min(total, c0 + a.cap);
+      __syncthreads();
+      for (int e = tid; e < c1 - c0; e += blockDim.x) {
+        const int gi = c0 + e;
+        int lo = 0, hi = NS - 1;  // slot s with s_pre[s] <= gi < s_pre[s+1]
+        while (lo < hi) {
+          const int mid = (lo + hi + 1) >> 1;
+          if (s_pre[mid] <= gi) lo = mid;
+          else hi = mid - 1;
+        }
+        const int s = lo;
+        const Atom4<T> at = sorted[s_start[s] + gi - s_pre[s]];
+        const int sx = s / (SW * SW), sy = (s / SW) % SW, sz = s % SW;
+        Atom4<T> o;
+        o.x = at.x + (T)sx + cen0;
+        o.y = at.y + (T)sy + cen0;
+        o.z = at.z + (T)sz + cen0;
+        o.q = at.q;
+        src[e] = o;
+      }
+      __syncthreads();
+      if (valid) {
+        for (int dx = 0; dx < 3; ++dx)
+          for (int dy = 0; dy < 3; ++dy)
+            for (int dz = 0; dz < 3; ++dz) {
+              const int s = ((lx + dx) * SW + (ly + dy)) * SW + (lz + dz);
+              const int j0 = max(s_pre[s], c0) - c0, j1 = min(s_pre[s + 1], c1) - c0;
+              for (int j = j0; j < j1; ++j) {
+                const Atom4<T> o = src[j];
+                const T rx = px - o.x, ry = py - o.y, rz = pz - o.z;
+                const T r2 = rx * rx + ry * ry + rz * rz;
+                const T ri = r2 > T(0) ? rsqrt_t<T>(r2) : T(0);
+                const T qr = o.q * ri;
+                phi += qr;
+                const T f = qr * ri * ri;
+                ex += f * rx;
+                ey += f * ry;
+                ez += f * rz;
+              }
+            }
+      }
+    }
+    if (valid) {
+      const T *Lm = loc + my * a.K;
+      T pf = T(0), gx = T(0), gy = T(0), gz = T(0);
+      const int p = a.p;
+      for_regular(p, me.x, me.y, me.z, [&](int nn, int m, T re, T im) {
+        const int i0 = ridx_d(nn, m, 0);
+        const T w = m ? T(2) : T(1);
+        pf += w * (Lm[i0] * re + (m ? Lm[i0 + 1] * im : T(0)));
+        if (nn < p) {
+          T xr, xi, yr, yi, zr, zi;
+          grad_coeffs(Lm, nn, m, xr, xi, yr, yi, zr, zi);
+          gx += w * (xr * re + xi * im);
+          gy += w * (yr * re + yi * im);
+          gz += w * (zr * re + zi * im);
+        }
+      });
+      double ph = ((double)phi + (double)pf) * inv_h;
+      double E[3] = {((double)ex - (double)gx) * inv_h * inv_h, ((double)ey - (double)gy) * inv_h * inv_h,
+                     ((double)ez - (double)gz) * inv_h * inv_h};
+      if (a.periodic) {
+        const double ax = (b0x + lx + 0.5 + (double)me.x) * h - half;
+        const double ay = (b0y + ly + 0.5 + (double)me.y) * h - half;
+        const double az = (b0z + lz + 0.5 + (double)me.z) * h - half;
+        ph += c_r2 * (g.Q * (ax * ax + ay * ay + az * az) - 2.0 * (g.D[0] * ax + g.D[1] * ay + g.D[2] * az) + g.S2);
+        E[0] += 2.0 * c_r2 * (g.D[0] - g.Q * ax);
+        E[1] += 2.0 * c_r2 * (g.D[1] - g.Q * ay);
+        E[2] += 2.0 * c_r2 * (g.D[2] - g.Q * az);
+      }
+      const double q = (double)me.q;
+      phi_sorted[ti] = (T)ph;
+      const int64_t u = perm[ti];
+      if (F) {
+        F[3 * u + 0] = (T)(a.ke * q * E[0]);
+        F[3 * u + 1] = (T)(a.ke * q * E[1]);
+        F[3 * u + 2] = (T)(a.ke * q * E[2]);
+      }
+      if (pot_user) pot_user[u] = (T)(a.ke * ph);
+      esum += q * ph;
+    }
+  }
+  for (int off = 32; off > 0; off >>= 1) esum += __shfl_xor(esum, off);
+  if ((tid & 63) == 0) s_red[tid >> 6] = esum;
+  __syncthreads();
+  if (tid == 0) {
+    double s = 0.0;
+    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) s += s_red[w];
+    epart[blockIdx.x] = s;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Charge scaling (paper, eq after eq constraint): qt = sum_r lt_r q^(s,r) at site atoms.
+// ---------------------------------------------------------------------------
+template <class T>
+__global__ void k_charge_scale(const int *__restrict__ atom_off, const int *__restrict__ form_off,
+                               const int *__restrict__ site_atoms, const double *__restrict__ fq,
+                               const int *__restrict__ fq_off, const double *__restrict__ lam, int n_sites,
+                               T *__restrict__ qt) {
+  const int s = blockIdx.x;
+  if (s >= n_sites) return;
+  const int na = atom_off[s + 1] - atom_off[s], nf = form_off[s + 1] - form_off[s];
+  for (int i = threadIdx.x; i < na; i += blockDim.x) {
+    double v = 0.0;
+    for (int r = 0; r < nf; ++r) v += lam[form_off[s] + r] * fq[fq_off[s] + r * na + i];
+    qt[site_atoms[atom_off[s] + i]] = (T)v;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// MAHI site correction, float64, one block of 64 threads per site.
+// Site kernel Phi_ij = sum over the 27 nearest images of 1/|r_ij + nL| (the
+// "box-box" part, computed directly as in an FMM of depth 0) + the truncated
+// lattice bilinear form that the tree applied to the pair + the r^2 part; the
+// same wrapped coordinates as the tree are used so that the correction
+// removes the tree's intra-site terms.  With U^r_i = sum_j Phi_ij q^r_j and
+// Ut = sum_r lt_r U^r (the site's own share of the scaled potential):
+//   C^r   = sum_i q^r_i (Ut_i - U^r_i / 2)                (correction, eq correction_scheme)
+//   dV/dlt_r = ke (sum_i q^r_i V_i - C^r)                  (per-form part of the mapping K)
+//   dE_s  = 1/2 (sum_r lt_r q^r.U^r - qt.Ut)               (HI minus charge-scaled intra-site energy)
+//   dF_i  = sum_r lt_r q^r_i W^r_i - qt_i Wt_i,  W = sum_j G_ij q_j, G = -grad_i Phi
+// ---------------------------------------------------------------------------
+template <class T>
+__global__ void __launch_bounds__(64) k_site(SiteArgs a, const T *__restrict__ xyz, const int *__restrict__ slot_of,
+                                             const T *__restrict__ phi_sorted, const Geom *__restrict__ gp,
+                                             const double *__restrict__ LamT, T *__restrict__ F,
+                                             double *__restrict__ dvdl, double *__restrict__ dE_site) {
+  extern __shared__ double sm[];
+  const int s = blockIdx.x, tid = threadIdx.x;
+  const int na = a.atom_off[s + 1] - a.atom_off[s], nf = a.form_off[s + 1] - a.form_off[s];
+  const int K = a.K, p = a.p;
+  __shared__ double x[kMaxSiteAtoms][3], V[kMaxSiteAtoms], qt[kMaxSiteAtoms], ut[kMaxSiteAtoms], lam[kMaxSiteForms];
+  __shared__ double qf[kMaxSiteForms][kMaxSiteAtoms];
+  __shared__ double U[kMaxSiteForms][kMaxSiteAtoms], W[kMaxSiteForms][kMaxSiteAtoms][3];
+  // dynamic: Rt[maxa][K] (unconjugated Rt at (x - c)/L), om[maxf][K] (site multipoles), Lat[maxf][K] (lattice locals)
+  double *Rt = sm;
+  double *om = Rt + a.maxa * K;
+  double *Lat = om + a.maxf * K;
+
+  const Geom g = *gp;
+  const double L = g.edge;
+  if (tid < na) {
+    const int atom = a.site_atoms[a.atom_off[s] + tid];
+    for (int d = 0; d < 3; ++d) {
+      const double xv = (double)xyz[3 * (int64_t)atom + d];
+      x[tid][d] = a.periodic ? wrap_coord(xv, L) : xv;
+    }
+    V[tid] = (double)phi_sorted[slot_of[atom]];
+  }
+  if (tid < nf) lam[tid] = a.lam[a.form_off[s] + tid];
+  for (int e = tid; e < nf * na; e += 64) {
+    const int r = e / na, i = e % na;
+    qf[r][i] = a.fq[a.fq_off[s] + r * na + i];
+  }
+  __syncthreads();
+  if (tid < na) {
+    double v = 0.0;
+    for (int r = 0; r < nf; ++r) v += lam[r] * qf[r][tid];
+    qt[tid] = v;
+  }
+  // direct part over the 27 nearest images (+ r^2 part when periodic), contracted with each form
+  const double c_r2 = a.periodic ? 2.0 * 3.14159265358979323846 / (3.0 * L * L * L) : 0.0;
+  const int R = a.periodic ? 1 : 0;
+  for (int e = tid; e < nf * na; e += 64) {
+    const int r = e / na, i = e % na;
+    double u = 0.0, w0 = 0.0, w1 = 0.0, w2 = 0.0;
+    for (int j = 0; j < na; ++j) {
+      const double rx = x[i][0] - x[j][0], ry = x[i][1] - x[j][1], rz = x[i][2] - x[j][2];
+      double ph = 0.0, gx = 0.0, gy = 0.0, gz = 0.0;
+      for (int ia = -R; ia <= R; ++ia)
+        for (int ib = -R; ib <= R; ++ib)
+          for (int ic = -R; ic <= R; ++ic) {
+            if (i == j && ia == 0 && ib == 0 && ic == 0) continue;
+            const double dx = rx + ia * L, dy = ry + ib * L, dz = rz + ic * L;
+            const double ri = 1.0 / sqrt(dx * dx + dy * dy + dz * dz);
+            ph += ri;
+            const double f = ri * ri * ri;
+            gx += f * dx;
+            gy += f * dy;
+            gz += f * dz;
+          }
+      if (a.periodic) {
+        ph += c_r2 * (rx * rx + ry * ry + rz * rz);
+        gx -= 2.0 * c_r2 * rx;
+        gy -= 2.0 * c_r2 * ry;
+        gz -= 2.0 * c_r2 * rz;
+      }
+      const double qj = qf[r][j];
+      u += ph * qj;
+      w0 += gx * qj;
+      w1 += gy * qj;
+      w2 += gz * qj;
+    }
+    U[r][i] = u;
+    W[r][i][0] = w0;
+    W[r][i][1] = w1;
+    W[r][i][2] = w2;
+  }
+  if (a.periodic) {
+    // lattice part: the tree's truncated lattice operator applied to the site's own charges
+    const double half = 0.5 * L, invL = 1.0 / L;
+    if (tid < na) {
+      double *row = Rt + tid * K;
+      for_regular(p, (x[tid][0] - half) * invL, (x[tid][1] - half) * invL, (x[tid][2] - half) * invL,
+                  [&](int n, int m, double re, double im) {
+                    const int i0 = ridx_d(n, m, 0);
+                    row[i0] = re;
+                    if (m) row[i0 + 1] = im;
+                  });
+    }
+    __syncthreads();
+    for (int e = tid; e < nf * K; e += 64) {
+      const int r = e / K, k = e % K;
+      // multipole = sum q conj(Rt): the imaginary slots (even, nonzero offset within a degree) flip sign
+      const int nd = (int)floor(sqrt((double)k) + 1e-9);
+      const int o = k - nd * nd;
+      const double sgn = (o > 0 && (o & 1) == 0) ? -1.0 : 1.0;
+      double v = 0.0;
+      for (int i = 0; i < na; ++i) v += qf[r][i] * Rt[i * K + k];
+      om[r * K + k] = sgn * v;
+    }
+    __syncthreads();
+    for (int e = tid; e < nf * K; e += 64) {
+      const int r = e / K, k = e % K;
+      double v = 0.0;
+      for (int c = 0; c < K; ++c) v += LamT[(int64_t)c * K + k] * om[r * K + c];
+      Lat[r * K + k] = v;
+    }
+    __syncthreads();
+    for (int e = tid; e < nf * na; e += 64) {
+      const int r = e / na, i = e % na;
+      const double *Rr = Rt + i * K;
+      const double *Lr = Lat + r * K;
+      double pot = 0.0, gx = 0.0, gy = 0.0, gz = 0.0;
+      for (int n = 0; n <= p; ++n)
+        for (int m = 0; m <= n; ++m) {
+          const int i0 = ridx_d(n, m, 0);
+          const double w = m ? 2.0 : 1.0;
+          const double rre = Rr[i0], rim = m ? Rr[i0 + 1] : 0.0;
+          pot += w * (Lr[i0] * rre + (m ? Lr[i0 + 1] * rim : 0.0));
+          if (n < p) {
+            double xr, xi, yr, yi, zr, zi;
+            grad_coeffs(Lr, n, m, xr, xi, yr, yi, zr, zi);
+            gx += w * (xr * rre + xi * rim);
+            gy += w * (yr * rre + yi * rim);
+            gz += w * (zr * rre + zi * rim);
+          }
+        }
+      U[r][i] += pot * invL;
+      W[r][i][0] -= gx * invL * invL;
+      W[r][i][1] -= gy * invL * invL;
+      W[r][i][2] -= gz * invL * invL;
+    }
+  }
+  __syncthreads();
+  // per-atom combination and force correction
+  if (tid < na) {
+    double u = 0.0, wt0 = 0.0, wt1 = 0.0, wt2 = 0.0, d0 = 0.0, d1 = 0.0, d2 = 0.0;
+    for (int r = 0; r < nf; ++r) {
+      u += lam[r] * U[r][tid];
+      wt0 += lam[r] * W[r][tid][0];
+      wt1 += lam[r] * W[r][tid][1];
+      wt2 += lam[r] * W[r][tid][2];
+      d0 += lam[r] * qf[r][tid] * W[r][tid][0];
+      d1 += lam[r] * qf[r][tid] * W[r][tid][1];
+      d2 += lam[r] * qf[r][tid] * W[r][tid][2];
+    }
+    d0 -= qt[tid] * wt0;
+    d1 -= qt[tid] * wt1;
+    d2 -= qt[tid] * wt2;
+    const int64_t atom = a.site_atoms[a.atom_off[s] + tid];
+    if (F) {
+      F[3 * atom + 0] = (T)((double)F[3 * atom + 0] + a.ke * d0);
+      F[3 * atom + 1] = (T)((double)F[3 * atom + 1] + a.ke * d1);
+      F[3 * atom + 2] = (T)((double)F[3 * atom + 2] + a.ke * d2);
+    }
+    ut[tid] = u;
+  }
+  __syncthreads();
+  if (tid < nf) {
+    const int r = tid;
+    double c = 0.0, vq = 0.0;
+    for (int i = 0; i < na; ++i) {
+      c += qf[r][i] * (ut[i] - 0.5 * U[r][i]);
+      vq += qf[r][i] * V[i];
+    }
+    if (dvdl) dvdl[a.form_off[s] + r] = a.ke * (vq - c);
+  }
+  if (tid == 0) {
+    double e = 0.0;
+    for (int r = 0; r < nf; ++r) {
+      double t = 0.0;
+      for (int i = 0; i < na; ++i) t += qf[r][i] * U[r][i];
+      e += lam[r] * t;
+    }
+    for (int i = 0; i < na; ++i) e -= qt[i] * ut[i];
+    dE_site[s] = 0.5 * e;
+  }
+}
+
+// E = ke (1/2 sum_blocks epart + sum_sites dE), fixed order.
+__global__ void __launch_bounds__(256) k_finalize(const double *__restrict__ epart, int nb,
+                                                  const double *__restrict__ dE_site, int ns, double ke,
+                                                  double *__restrict__ E) {
+  __shared__ double s[256];
+  double v = 0.0, w = 0.0;
+  for (int i = threadIdx.x; i < nb; i += 256) v += epart[i];
+  for (int i = threadIdx.x; i < ns; i += 256) w += dE_site[i];
+  s[threadIdx.x] = 0.5 * v + w;
+  __syncthreads();
+  for (int k = 128; k > 0; k >>= 1) {
+    if ((int)threadIdx.x < k) s[threadIdx.x] += s[threadIdx.x + k];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *E = ke * s[0];
+}
+
+// ---------------------------------------------------------------------------
+// Host launchers
+// ---------------------------------------------------------------------------
+static inline int grid_for(int64_t n, int bs) {
+  int64_t g = (n + bs - 1) / bs;
+  if (g > 65535 * 8) g = 65535 * 8;
+  if (g < 1) g = 1;
+  return (int)g;
+}
+
+void launch_fill_i32(int *p, int v, int64_t n, hipStream_t st) {
+  hipLaunchKernelGGL(k_fill_i32, dim3(grid_for(n, 256)), dim3(256), 0, st, p, v, n);
+}
+
+template <class T>
+void launch_bbox(const T *xyz, int64_t n, double *part, int nblk, Geom *g, hipStream_t st) {
+  hipLaunchKernelGGL(k_bbox_partial<T>, dim3(nblk), dim3(256), 0, st, xyz, n, part);
+  hipLaunchKernelGGL(k_bbox_final, dim3(1), dim3(64), 0, st, part, nblk, g);
+}
+
+template <class T>
+void launch_tree(const T *xyz, const T *qt, int64_t n, const Geom *g, int d, int periodic, TreeBufs<T> b,
+                 hipStream_t st) {
+  const int nleaf = 1 << (3 * d);
+  launch_fill_i32(b.count, 0, nleaf, st);
+  hipLaunchKernelGGL(k_bin<T>, dim3(grid_for(n, 256)), dim3(256), 0, st, xyz, n, g, d, periodic, b.key, b.count);
+  hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, st, b.count, b.start, b.cursor, nleaf);
+  hipLaunchKernelGGL(k_scatter, dim3(grid_for(n, 256)), dim3(256), 0, st, b.key, b.cursor, b.tmp, n);
+  hipLaunchKernelGGL(k_leafsort<T>, dim3((nleaf + 3) / 4), dim3(256), 0, st, b.tmp, b.start, nleaf, xyz, qt, g, d,
+                     periodic, b.perm, b.slot_of, b.sorted);
+}
+
+template <class T>
+void launch_p2m(const Atom4<T> *sorted, const int *start, int nleaf, int p, T *Mleaf, double *qds, const Geom *g, int d,
+                hipStream_t st) {
+  const int K = (p + 1) * (p + 1);
+  int chunk = (int)(16384 / (K * sizeof(T)));
+  if (chunk > 64) chunk = 64;
+  if (chunk < 1) chunk = 1;
+  hipLaunchKernelGGL(k_p2m<T>, dim3(nleaf), dim3(64), chunk * K * sizeof(T), st, sorted, start, p, K, chunk, Mleaf, qds,
+                     g, d);
+}
+
+static int pb_for(int K, size_t elem, int per_parent) {
+  int pb = (int)(32768 / (per_parent * K * elem));
+  return pb < 1 ? 1 : (pb > 8 ? 8 : pb);
+}
+
+template <class T>
+void launch_m2m(T *M, int lp, int K, const T *Tm, hipStream_t st) {
+  const int PB = pb_for(K, sizeof(T), 8);
+  const int64_t np = int64_t(1) << (3 * lp);
+  hipLaunchKernelGGL(k_m2m<T>, dim3((unsigned)((np + PB - 1) / PB)), dim3(128), PB * 8 * K * sizeof(T), st, M, lp, K,
+                     Tm, PB);
+}
+
+template <class T>
+void launch_l2l(T *L, int lc, int K, const T *Tl, hipStream_t st) {
+  const int PB = pb_for(K, sizeof(T), 1);
+  const int64_t np = int64_t(1) << (3 * (lc - 1));
+  hipLaunchKernelGGL(k_l2l<T>, dim3((unsigned)((np + PB - 1) / PB)), dim3(128), PB * K * sizeof(T), st, L, lc, K, Tl, PB);
+}
+
+template <class T>
+void launch_lattice(const T *M, T *L, const double *LamT, int K, const double *qds, int nleaf, Geom *g, hipStream_t st) {
+  hipLaunchKernelGGL(k_lattice<T>, dim3(1), dim3(256), 0, st, M, L, LamT, K, qds, nleaf, g);
+}
+
+template <class T>
+void m2l_plan(int p, int d, int periodic, M2LArgs &a, int &blocks, int &threads, size_t &lds) {
+  using MF = Mfma<T>;
+  a.K = (p + 1) * (p + 1);
+  a.KK = (a.K + MF::TK - 1) / MF::TK * MF::TK;
+  a.nrt = (a.K + MF::TM - 1) / MF::TM;
+  a.RP = a.nrt * MF::TM;
+  a.ngroups = (a.nrt + 3) / 4;
+  a.nw = (a.nrt + a.ngroups - 1) / a.ngroups;
+  a.d = d;
+  a.periodic = periodic;
+  a.lmin = periodic ? 1 : 2;
+  const int budget = 40960;
+  int kc = budget / (kBStride * (int)sizeof(T));
+  kc = kc / MF::TK * MF::TK;
+  if (kc > a.KK) kc = a.KK;
+  a.kc = kc;
+  blocks = 0;
+  for (int l = 0; l <= 8; ++l) a.level_start[l] = 0;
+  for (int l = a.lmin; l <= d; ++l) {
+    a.level_start[l] = blocks;
+    const int64_t np = int64_t(1) << (3 * (l - 1));
+    blocks += (int)(8 * ((np + 63) / 64) * a.ngroups);
+  }
+  if (d + 1 <= 8) a.level_start[d + 1 <= 8 ? d + 1 : 8] = blocks;
+  threads = a.nw * 64;
+  lds = (size_t)a.kc * kBStride * sizeof(T);
+}
+
+template <class T>
+void m2l_table_layout(int p, int &KK, int &RP) {
+  using MF = Mfma<T>;
+  const int K = (p + 1) * (p + 1);
+  KK = (K + MF::TK - 1) / MF::TK * MF::TK;
+  RP = (K + MF::TM - 1) / MF::TM * MF::TM;
+}
+
+template <class T>
+void launch_m2l(const T *M, T *L, const T *Tab, const int4 *lists, int p, int d, int periodic, hipStream_t st) {
+  M2LArgs a;
+  int blocks, threads;
+  size_t lds;
+  m2l_plan<T>(p, d, periodic, a, blocks, threads, lds);
+  if (blocks == 0) return;
+  hipLaunchKernelGGL(k_m2l<T>, dim3(blocks), dim3(threads), lds, st, M, L, Tab, lists, a);
+}
+
+template <class T>
+void launch_m2l_valu(const T *M, T *L, const T *Tab, const int4 *lists, int p, int d, int periodic, hipStream_t st) {
+  M2LArgs a;
+  int blocks, threads;
+  size_t lds;
+  m2l_plan<T>(p, d, periodic, a, blocks, threads, lds);
+  if (blocks == 0) return;
+  blocks /= a.ngroups;
+  for (int l = a.lmin; l <= d + 1 && l <= 8; ++l) a.level_start[l] /= a.ngroups;
+  hipLaunchKernelGGL(k_m2l_valu<T>, dim3(blocks), dim3(256), (size_t)2 * 64 * a.K * sizeof(T), st, M, L, Tab, lists, a);
+}
+
+template <class T>
+void launch_mfma_probe(const T *A, const T *B, T *C, int rows, int kk, hipStream_t st) {
+  using MF = Mfma<T>;
+  hipLaunchKernelGGL(k_mfma_probe<T>, dim3(1), dim3(64 * (rows / MF::TM)), 0, st, A, B, C, rows, kk);
+}
+
+template <class T>
+int p2p_blocks(int d) {
+  return d >= 1 ? 1 << (3 * (d - 1)) : 1;
+}
+
+template <class T>
+void launch_p2p(const Atom4<T> *sorted, const int *start, const int *perm, const T *Lleaf, const Geom *g, int d,
+                int periodic, int p, double ke, T *phi_sorted, T *F, T *pot_user, double *epart, hipStream_t st) {
+  P2PArgs a;
+  a.d = d;
+  a.periodic = periodic;
+  a.p = p;
+  a.K = (p + 1) * (p + 1);
+  a.ke = ke;
+  a.cap = (int)(40960 / sizeof(Atom4<T>));
+  const size_t lds = a.cap * sizeof(Atom4<T>) + (size_t)8 * a.K * sizeof(T);
+  hipLaunchKernelGGL(k_p2p_l2p<T>, dim3(p2p_blocks<T>(d)), dim3(256), lds, st, sorted, start, perm, Lleaf, g, a,
+                     phi_sorted, F, pot_user, epart);
+}
+
+template <class T>
+void launch_charge_scale(const SiteArgs &s, const double *lam, T *qt, hipStream_t st) {
+  if (s.n_sites == 0) return;
+  hipLaunchKernelGGL(k_charge_scale<T>, dim3(s.n_sites), dim3(64), 0, st, s.atom_off, s.form_off, s.site_atoms, s.fq,
+                     s.fq_off, lam, s.n_sites, qt);
+}
+
+size_t site_lds_bytes(int p, int maxa, int maxf) {
+  const int K = (p + 1) * (p + 1);
+  return sizeof(double) * ((size_t)maxa * K + 2 * (size_t)maxf * K);
+}
+
+template <class T>
+void launch_site(const SiteArgs &s, const T *xyz, const int *slot_of, const T *phi_sorted, const Geom *g,
+                 const double *LamT, T *F, double *dvdl, double *dE_site, hipStream_t st) {
+  if (s.n_sites == 0) return;
+  const size_t lds = site_lds_bytes(s.p, s.maxa, s.maxf);
+  hipLaunchKernelGGL(k_site<T>, dim3(s.n_sites), dim3(64), lds, st, s, xyz, slot_of, phi_sorted, g, LamT, F, dvdl,
+                     dE_site);
+}
+
+void launch_finalize(const double *epart, int nb, const double *dE_site, int ns, double ke, double *E, hipStream_t st) {
+  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(256), 0, st, epart, nb, dE_site, ns, ke, E);
+}
+
+
+#define MAHI_INST(T)                                                                                                 \
+  template void launch_bbox<T>(const T *, int64_t, double *, int, Geom *, hipStream_t);                             \
+  template void launch_tree<T>(const T *, const T *, int64_t, const Geom *, int, int, TreeBufs<T>, hipStream_t);     \
+  template void launch_p2m<T>(const Atom4<T> *, const int *, int, int, T *, double *, const Geom *, int, hipStream_t); \
+  template void launch_m2m<T>(T *, int, int, const T *, hipStream_t);                                               \
+  template void launch_l2l<T>(T *, int, int, const T *, hipStream_t);                                               \
+  template void launch_lattice<T>(const T *, T *, const double *, int, const double *, int, Geom *, hipStream_t);    \
+  template void launch_m2l<T>(const T *, T *, const T *, const int4 *, int, int, int, hipStream_t);                 \
+  template void m2l_table_layout<T>(int, int &, int &);                                                               \
+  template void launch_mfma_probe<T>(const T *, const T *, T *, int, int, hipStream_t);                              \
+  template void launch_m2l_valu<T>(const T *, T *, const T *, const int4 *, int, int, int, hipStream_t);                              \
+  template int p2p_blocks<T>(int);                                                                                   \
+  template void launch_p2p<T>(const Atom4<T> *, const int *, const int *, const T *, const Geom *, int, int, int,    \
+                              double, T *, T *, T *, double *, hipStream_t);                                         \
+  template void launch_charge_scale<T>(const SiteArgs &, const double *, T *, hipStream_t);                          \
+  template void launch_site<T>(const SiteArgs &, const T *, const int *, const T *, const Geom *, const double *,    \
+                               T *, double *, double *, hipStream_t);
+
+MAHI_INST(float)
+MAHI_INST(double)
+
+}  // namespace mahi

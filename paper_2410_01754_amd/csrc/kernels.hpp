@@ -1,0 +1,66 @@
+// Host-visible launch functions of the gfx950 kernels (kernels.hip).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "device_common.hpp"
+
+namespace mahi {
+
+struct M2LArgs {
+  int K, KK, RP, nrt, nw, ngroups, kc;
+  int d, lmin, periodic;
+  int level_start[9];
+};
+
+struct P2PArgs {
+  int d, periodic, p, K, cap;
+  double ke;
+};
+
+struct SiteArgs {
+  int n_sites, p, K, periodic, maxa, maxf;
+  double ke;
+  const int *atom_off;    // [M+1] offsets into site_atoms
+  const int *form_off;    // [M+1] offsets into the flat form list
+  const int *fq_off;      // [M]   offsets into fq
+  const int *site_atoms;  // [sum atoms]
+  const double *fq;       // per site: form-major, atom-minor charges
+  const double *lam;      // [sum forms]
+};
+
+template <class T>
+struct TreeBufs {
+  int *key, *count, *start, *cursor, *tmp, *perm, *slot_of;
+  Atom4<T> *sorted;
+};
+
+hipError_t upload_constants();
+void launch_fill_i32(int *p, int v, int64_t n, hipStream_t st);
+template <class T> void launch_bbox(const T *xyz, int64_t n, double *part, int nblk, Geom *g, hipStream_t st);
+template <class T>
+void launch_tree(const T *xyz, const T *qt, int64_t n, const Geom *g, int d, int periodic, TreeBufs<T> b, hipStream_t st);
+template <class T>
+void launch_p2m(const Atom4<T> *sorted, const int *start, int nleaf, int p, T *Mleaf, double *qds, const Geom *g, int d,
+                hipStream_t st);
+template <class T> void launch_m2m(T *M, int lp, int K, const T *Tm, hipStream_t st);
+template <class T> void launch_l2l(T *L, int lc, int K, const T *Tl, hipStream_t st);
+template <class T>
+void launch_lattice(const T *M, T *L, const double *LamT, int K, const double *qds, int nleaf, Geom *g, hipStream_t st);
+template <class T> void m2l_table_layout(int p, int &KK, int &RP);
+template <class T>
+void launch_m2l(const T *M, T *L, const T *Tab, const int4 *lists, int p, int d, int periodic, hipStream_t st);
+template <class T>
+void launch_m2l_valu(const T *M, T *L, const T *Tab, const int4 *lists, int p, int d, int periodic, hipStream_t st);
+template <class T> void launch_mfma_probe(const T *A, const T *B, T *C, int rows, int kk, hipStream_t st);
+template <class T> int p2p_blocks(int d);
+template <class T>
+void launch_p2p(const Atom4<T> *sorted, const int *start, const int *perm, const T *Lleaf, const Geom *g, int d,
+                int periodic, int p, double ke, T *phi_sorted, T *F, T *pot_user, double *epart, hipStream_t st);
+template <class T> void launch_charge_scale(const SiteArgs &s, const double *lam, T *qt, hipStream_t st);
+template <class T>
+void launch_site(const SiteArgs &s, const T *xyz, const int *slot_of, const T *phi_sorted, const Geom *g,
+                 const double *LamT, T *F, double *dvdl, double *dE_site, hipStream_t st);
+void launch_finalize(const double *epart, int nb, const double *dE_site, int ns, double ke, double *E, hipStream_t st);
+size_t site_lds_bytes(int p, int maxa, int maxf);
+
+}  // namespace mahi

@@ -1,0 +1,223 @@
+"""ctypes binding of libmahi.so (argument marshalling only).
+
+Every step of an evaluation runs in the library's HIP kernels; this module
+only converts Python/numpy/torch arguments into the C structs of
+include/mahi.h.  Importing it without the built library raises at once: there
+is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional, Sequence
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libmahi.so")
+
+MAHI_DEVICE_IO = 1
+N_STAGES = 9
+STATUS = {0: "MAHI_OK", -1: "MAHI_EINVAL", -2: "MAHI_ENOMEM", -3: "MAHI_EDEVICE", -4: "MAHI_ERANGE",
+          -5: "MAHI_ESTATE", -6: "MAHI_EUNSUPPORTED"}
+
+
+class MahiError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"{STATUS.get(status, status)}: {message}")
+        self.status = status
+
+
+class _Box(ctypes.Structure):
+    _fields_ = [("edge", ctypes.c_double), ("periodic", ctypes.c_int)]
+
+
+class _Sites(ctypes.Structure):
+    _fields_ = [("n_sites", ctypes.c_int32), ("forms_per_site", ctypes.POINTER(ctypes.c_int32)),
+                ("atoms_per_site", ctypes.POINTER(ctypes.c_int32)), ("site_atoms", ctypes.POINTER(ctypes.c_int32)),
+                ("form_charges", ctypes.POINTER(ctypes.c_double))]
+
+
+class _Opts(ctypes.Structure):
+    _fields_ = [("order", ctypes.c_int), ("depth", ctypes.c_int), ("precision", ctypes.c_int),
+                ("coulomb_k", ctypes.c_double), ("hip_stream", ctypes.c_void_p)]
+
+
+class _EvalArgs(ctypes.Structure):
+    _fields_ = [("xyz", ctypes.c_void_p), ("energy", ctypes.c_void_p), ("forces", ctypes.c_void_p),
+                ("dvdl", ctypes.c_void_p), ("potential", ctypes.c_void_p), ("flags", ctypes.c_uint32)]
+
+
+def load(path: str = LIB_PATH) -> ctypes.CDLL:
+    if not os.path.exists(path):
+        raise ImportError(f"libmahi.so not built at {path}; run python -m paper_2410_01754_amd.build")
+    lib = ctypes.CDLL(path)
+    vp = ctypes.c_void_p
+    lib.mahi_create.argtypes = [ctypes.POINTER(vp), ctypes.POINTER(_Box), ctypes.c_int64,
+                                ctypes.POINTER(ctypes.c_double), ctypes.POINTER(_Sites), ctypes.POINTER(_Opts)]
+    lib.mahi_create.restype = ctypes.c_int
+    lib.mahi_set_lambda.argtypes = [vp, ctypes.POINTER(ctypes.c_double)]
+    lib.mahi_set_lambda.restype = ctypes.c_int
+    lib.mahi_eval.argtypes = [vp, ctypes.POINTER(_EvalArgs)]
+    lib.mahi_eval.restype = ctypes.c_int
+    lib.mahi_destroy.argtypes = [vp]
+    lib.mahi_destroy.restype = None
+    lib.mahi_strerror.argtypes = [ctypes.c_int]
+    lib.mahi_strerror.restype = ctypes.c_char_p
+    lib.mahi_last_error.argtypes = [vp]
+    lib.mahi_last_error.restype = ctypes.c_char_p
+    lib.mahi_info.argtypes = [vp, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int32),
+                              ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int),
+                              ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)]
+    lib.mahi_info.restype = ctypes.c_int
+    lib.mahi_host_selftest.argtypes = [ctypes.c_int, ctypes.POINTER(ctypes.c_double)]
+    lib.mahi_host_selftest.restype = ctypes.c_int
+    lib.mahi_device_selftest.argtypes = [ctypes.c_int, ctypes.POINTER(ctypes.c_double)]
+    lib.mahi_device_selftest.restype = ctypes.c_int
+    lib.mahi_profile_begin.argtypes = [vp, ctypes.c_int]
+    lib.mahi_profile_begin.restype = ctypes.c_int
+    lib.mahi_profile_end.argtypes = [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int)]
+    lib.mahi_profile_end.restype = ctypes.c_int
+    lib.mahi_stage_name.argtypes = [ctypes.c_int]
+    lib.mahi_stage_name.restype = ctypes.c_char_p
+    lib.mahi_debug_copy.argtypes = [vp, ctypes.c_int, vp, ctypes.c_int64]
+    lib.mahi_debug_copy.restype = ctypes.c_int
+    return lib
+
+
+_lib: Optional[ctypes.CDLL] = None
+
+
+def lib() -> ctypes.CDLL:
+    global _lib
+    if _lib is None:
+        _lib = load()
+    return _lib
+
+
+def _check(status: int, ctx=None):
+    if status != 0:
+        msg = lib().mahi_last_error(ctx).decode()
+        raise MahiError(status, msg)
+
+
+def host_selftest(order: int) -> float:
+    v = ctypes.c_double()
+    _check(lib().mahi_host_selftest(order, ctypes.byref(v)))
+    return v.value
+
+
+def device_selftest(precision: int) -> float:
+    v = ctypes.c_double()
+    _check(lib().mahi_device_selftest(precision, ctypes.byref(v)))
+    return v.value
+
+
+def _ptr(a: np.ndarray, t):
+    return a.ctypes.data_as(ctypes.POINTER(t))
+
+
+class Mahi:
+    """One MAHI evaluator: a cubic box, N charges and their titratable sites.
+
+    sites: sequence of (atoms [n] int, form_charges [n_forms, n] float).
+    """
+
+    def __init__(self, edge: float, periodic: bool, charges, sites: Sequence = (), order: int = 8, depth: int = 3,
+                 precision: int = 32, coulomb_k: float = 0.0, stream: Optional[int] = None):
+        self._lib = lib()
+        q = np.ascontiguousarray(charges, dtype=np.float64)
+        self.n = int(q.shape[0])
+        self.precision = int(precision)
+        self.dtype = np.float32 if precision == 32 else np.float64
+        fps = np.array([np.asarray(c).shape[0] for _, c in sites], dtype=np.int32)
+        aps = np.array([len(a) for a, _ in sites], dtype=np.int32)
+        atoms = np.ascontiguousarray(np.concatenate([np.asarray(a) for a, _ in sites]) if len(sites) else
+                                     np.zeros(0), dtype=np.int32)
+        fq = np.ascontiguousarray(np.concatenate([np.asarray(c, dtype=np.float64).reshape(-1) for _, c in sites])
+                                  if len(sites) else np.zeros(0), dtype=np.float64)
+        self.n_forms = int(fps.sum())
+        self._keep = (q, fps, aps, atoms, fq)
+        box = _Box(float(edge), 1 if periodic else 0)
+        st = _Sites(len(sites), _ptr(fps, ctypes.c_int32), _ptr(aps, ctypes.c_int32), _ptr(atoms, ctypes.c_int32),
+                    _ptr(fq, ctypes.c_double))
+        opts = _Opts(int(order), int(depth), int(precision), float(coulomb_k), ctypes.c_void_p(stream or 0))
+        h = ctypes.c_void_p()
+        _check(self._lib.mahi_create(ctypes.byref(h), ctypes.byref(box), self.n, _ptr(q, ctypes.c_double),
+                                     ctypes.byref(st), ctypes.byref(opts)), None)
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            self._lib.mahi_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_lambda(self, lam_tilde):
+        lt = np.ascontiguousarray(lam_tilde, dtype=np.float64)
+        if lt.shape[0] != self.n_forms:
+            raise ValueError("lambda_tilde has the wrong length")
+        _check(self._lib.mahi_set_lambda(self._h, _ptr(lt, ctypes.c_double)), self._h)
+
+    def eval(self, xyz, forces: bool = True, dvdl: bool = True, potential: bool = False):
+        """Host-memory evaluation; returns dict(energy, forces, dvdl, potential)."""
+        x = np.ascontiguousarray(xyz, dtype=self.dtype)
+        if x.shape != (self.n, 3):
+            raise ValueError("xyz must have shape (N, 3)")
+        E = np.zeros(1)
+        F = np.zeros((self.n, 3), dtype=self.dtype) if forces else None
+        dv = np.zeros(self.n_forms) if (dvdl and self.n_forms) else None
+        pot = np.zeros(self.n, dtype=self.dtype) if potential else None
+        args = _EvalArgs(x.ctypes.data, E.ctypes.data, None if F is None else F.ctypes.data,
+                         None if dv is None else dv.ctypes.data, None if pot is None else pot.ctypes.data, 0)
+        _check(self._lib.mahi_eval(self._h, ctypes.byref(args)), self._h)
+        return {"energy": float(E[0]), "forces": F, "dvdl": dv, "potential": pot}
+
+    def eval_device(self, xyz_ptr: int, energy_ptr: int, forces_ptr: int = 0, dvdl_ptr: int = 0,
+                    potential_ptr: int = 0):
+        """Asynchronous evaluation on device pointers (e.g. torch tensor data_ptr())."""
+        args = _EvalArgs(xyz_ptr, energy_ptr or None, forces_ptr or None, dvdl_ptr or None, potential_ptr or None,
+                         MAHI_DEVICE_IO)
+        _check(self._lib.mahi_eval(self._h, ctypes.byref(args)), self._h)
+
+    def profile_begin(self, max_evals: int):
+        _check(self._lib.mahi_profile_begin(self._h, int(max_evals)), self._h)
+
+    def profile_end(self):
+        """Mean ms per stage over the evaluations since profile_begin: (dict, n_evals)."""
+        ms = (ctypes.c_double * N_STAGES)()
+        n = ctypes.c_int()
+        _check(self._lib.mahi_profile_end(self._h, ms, ctypes.byref(n)), self._h)
+        return {self._lib.mahi_stage_name(i).decode(): ms[i] for i in range(N_STAGES)}, n.value
+
+    def debug_copy(self, which: int, count: int):
+        """Copy an internal buffer of the last evaluation (test hook; see mahi_debug_copy)."""
+        dt = np.int32 if which in (2, 3) else self.dtype
+        out = np.zeros(count, dtype=dt)
+        _check(self._lib.mahi_debug_copy(self._h, which, out.ctypes.data, count), self._h)
+        return out
+
+    def info(self):
+        n = ctypes.c_int64()
+        ns, nf = ctypes.c_int32(), ctypes.c_int32()
+        o, d, p = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+        _check(self._lib.mahi_info(self._h, ctypes.byref(n), ctypes.byref(ns), ctypes.byref(nf), ctypes.byref(o),
+                                   ctypes.byref(d), ctypes.byref(p)), self._h)
+        return dict(n_atoms=n.value, n_sites=ns.value, n_forms=nf.value, order=o.value, depth=d.value,
+                    precision=p.value)
+
+
+def from_system(system, precision: int = 32, order: Optional[int] = None, depth: Optional[int] = None,
+                coulomb_k: float = 0.0, stream: Optional[int] = None) -> Mahi:
+    """Build an evaluator for a synth.System-like object (x, q, sites, box, periodic)."""
+    sites = [(s.atoms, s.charges) for s in system.sites]
+    m = Mahi(system.box, system.periodic, system.q, sites, order=system.order if order is None else order,
+             depth=system.depth if depth is None else depth, precision=precision, coulomb_k=coulomb_k, stream=stream)
+    if system.sites:
+        m.set_lambda(system.lam_flat())
+    return m

@@ -1,0 +1,87 @@
+"""C-ABI contract checks that need no GPU: the library loads, exports every
+symbol include/mahi.h declares, validates arguments before touching a device,
+and its float64 operator tables pass their host self-test."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import paper_2410_01754_amd as pkg
+from paper_2410_01754_amd import mahi as mb
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_symbols():
+    text = open(os.path.join(ROOT, "include", "mahi.h")).read()
+    return sorted(set(re.findall(r"\b(mahi_[a-z_]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_symbol():
+    lib = mb.load()
+    names = declared_symbols()
+    assert len(names) >= 9
+    for n in names:
+        assert hasattr(lib, n), n
+
+
+def test_strerror_covers_all_codes():
+    lib = mb.load()
+    for code in (0, -1, -2, -3, -4, -5, -6):
+        assert lib.mahi_strerror(code).decode() != "unknown status"
+
+
+@pytest.mark.parametrize("order,bound", [(4, 1e-4), (8, 1e-8), (12, 1e-11), (16, 1e-12)])
+def test_host_tables_selftest(order, bound):
+    assert pkg.host_selftest(order) < bound
+
+
+def _create(edge=1.0, periodic=1, n=4, q=None, sites=None, order=8, depth=1, precision=32, k=0.0):
+    lib = mb.load()
+    q = np.ones(n) if q is None else np.asarray(q, dtype=np.float64)
+    h = ctypes.c_void_p()
+    box = mb._Box(edge, periodic)
+    opts = mb._Opts(order, depth, precision, k, None)
+    st = None
+    keep = []
+    if sites is not None:
+        fps, aps, atoms, fq = sites
+        arrs = [np.asarray(fps, np.int32), np.asarray(aps, np.int32), np.asarray(atoms, np.int32),
+                np.asarray(fq, np.float64)]
+        keep.extend(arrs)
+        st = mb._Sites(len(fps), mb._ptr(arrs[0], ctypes.c_int32), mb._ptr(arrs[1], ctypes.c_int32),
+                       mb._ptr(arrs[2], ctypes.c_int32), mb._ptr(arrs[3], ctypes.c_double))
+    r = lib.mahi_create(ctypes.byref(h), ctypes.byref(box), n, mb._ptr(q, ctypes.c_double),
+                        ctypes.byref(st) if st is not None else None, ctypes.byref(opts))
+    return r, lib.mahi_last_error(None).decode()
+
+
+@pytest.mark.parametrize("kw,code", [
+    (dict(n=0), -4),
+    (dict(order=0), -4),
+    (dict(order=21), -4),
+    (dict(depth=8), -4),
+    (dict(precision=16), -1),
+    (dict(edge=0.0), -1),
+    (dict(edge=float("nan")), -1),
+    (dict(periodic=2), -1),
+    (dict(q=[1.0, float("inf"), 0.0, 0.0]), -1),
+    (dict(sites=([2], [2], [0, 4], [0.1, 0.2, 0.3, 0.4])), -1),          # atom index out of range
+    (dict(sites=([2, 2], [2, 2], [0, 1, 1, 2], [0.1] * 8)), -1),         # overlapping sites
+    (dict(sites=([17], [1], [0], [0.1] * 17)), -4),                      # too many forms
+    (dict(sites=([2], [1], [0], [0.1, float("nan")])), -1),              # non-finite form charge
+])
+def test_create_validates_before_device(kw, code):
+    r, msg = _create(**kw)
+    assert r == code, msg
+    assert msg
+
+
+def test_create_without_gpu_reports_device_error():
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    r, msg = _create()
+    assert r == -3

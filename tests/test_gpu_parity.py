@@ -1,0 +1,193 @@
+"""Parity of the HIP path with the CPU oracle (run on an MI355X).
+
+Every comparison uses the same seeded float32 coordinates on both sides.  The
+error measure is the relative RMS ||a - b|| / ||b|| over all compared values.
+Tolerances: float64 path at depth 0 reproduces the oracle to rounding (the
+paper's depth-0 identity); at depth > 0 results carry the multipole truncation
+error, bounded by 2e-4 at p = 8 for forces and dE/dlambda-tilde.
+"""
+import os
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import hi, kernels
+from synth import make_config, make_system
+
+pytestmark = pytest.mark.gpu
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+def rel(a, b):
+    a, b = np.asarray(a, float), np.asarray(b, float)
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def gpu_eval(system, precision, order, depth, potential=False):
+    import paper_2410_01754_amd as pkg
+    print(f"[gpu] {system.name} N={system.n_atoms} p={order} d={depth} prec={precision}", flush=True)
+    m = pkg.from_system(system, precision=precision, order=order, depth=depth)
+    out = m.eval(system.x, potential=potential)
+    m.close()
+    return out
+
+
+_ORACLE = {}
+
+
+def oracle(system):
+    key = (system.name, system.seed, system.n_atoms, system.periodic)
+    if key not in _ORACLE:
+        if system.periodic:
+            _ORACLE[key] = hi.hi_periodic(system.x, system.q, system.sites, system.box)
+        else:
+            Phi, G = kernels.open_dense(system.x)
+            _ORACLE[key] = hi.hi_dense(system.q, system.sites, Phi, G)
+    return _ORACLE[key]
+
+
+def small_periodic(seed=31, edge=2.4, clustered=True):
+    nw = int(33.4 * edge ** 3)
+    return make_system(nw, edge, True, [6, 8, 5, 7], [2, 3, 2, 4], qrange=(-0.9, 0.9), total_step=None,
+                       clustered=clustered, simplex=True, depth=2, seed=seed, name=f"periodic{edge}")
+
+
+# ------------------------------------------------------------------ tile layout
+
+@pytest.mark.parametrize("prec,tol", [(32, 1e-5), (64, 1e-13)])
+def test_matrix_core_tile_layout(prec, tol):
+    import paper_2410_01754_amd as pkg
+    assert pkg.device_selftest(prec) < tol
+
+
+# ------------------------------------------------------------------ open boundaries (config 0)
+
+def test_open_depth0_float64_reproduces_oracle():
+    """Depth 0: every interaction and every correction is direct (paper's depth-0 identity)."""
+    s = make_config(0)
+    E, F, dv, _ = oracle(s)
+    g = gpu_eval(s, 64, 8, 0)
+    assert abs(g["energy"] - E) <= 1e-12 * abs(E)
+    assert rel(g["forces"], F) <= 1e-12
+    assert rel(g["dvdl"], dv) <= 1e-12
+
+
+@pytest.mark.parametrize("prec", [64, 32])
+def test_open_config0_depth2_p8(prec):
+    s = make_config(0)
+    E, F, dv, _ = oracle(s)
+    g = gpu_eval(s, prec, 8, 2)
+    print("open d2 p8", prec, abs(g["energy"] - E) / abs(E), rel(g["forces"], F), rel(g["dvdl"], dv))
+    assert rel(g["forces"], F) <= 2e-4
+    assert rel(g["dvdl"], dv) <= 2e-4
+    assert abs(g["energy"] - E) <= 2e-4 * abs(E)
+
+
+def test_open_order_convergence_float64():
+    s = make_config(0)
+    E, F, dv, _ = oracle(s)
+    errs = []
+    for p in (4, 8, 12, 16):
+        g = gpu_eval(s, 64, p, 2)
+        errs.append(rel(g["forces"], F))
+    print("open p-sweep", errs)
+    # truncation error of the well-separation-1 FMM falls ~16x per 4 orders
+    assert errs[1] < errs[0] / 8 and errs[2] < errs[1] / 8 and errs[3] < errs[2] / 8
+    assert errs[3] <= 3e-7
+
+
+# ------------------------------------------------------------------ periodic
+
+@pytest.mark.parametrize("depth", [0, 1, 2])
+def test_periodic_small_float64(depth):
+    """Depth 0 carries only the lattice truncation; deeper trees add M2L truncation."""
+    s = small_periodic()
+    E, F, dv, _ = oracle(s)
+    g = gpu_eval(s, 64, 12, depth)
+    print("periodic fp64 p12 d", depth, abs(g["energy"] - E) / abs(E), rel(g["forces"], F), rel(g["dvdl"], dv))
+    tol = 1e-5
+    assert abs(g["energy"] - E) <= tol * abs(E)
+    assert rel(g["forces"], F) <= tol
+    assert rel(g["dvdl"], dv) <= tol
+
+
+def test_periodic_order_convergence_float64():
+    s = small_periodic(seed=32)
+    E, F, dv, _ = oracle(s)
+    errs = []
+    for p in (4, 8, 12, 16):
+        g = gpu_eval(s, 64, p, 2)
+        errs.append((rel(g["forces"], F), rel(g["dvdl"], dv)))
+    print("periodic p-sweep", errs)
+    for k in range(3):
+        assert errs[k + 1][0] < errs[k][0] / 8 and errs[k + 1][1] < errs[k][1] / 8
+    assert errs[3][0] <= 3e-7 and errs[3][1] <= 1e-6
+
+
+@pytest.mark.parametrize("prec", [32, 64])
+def test_periodic_small_p8(prec):
+    s = small_periodic(seed=33, clustered=False)
+    E, F, dv, _ = oracle(s)
+    g = gpu_eval(s, prec, 8, 2)
+    print("periodic p8", prec, abs(g["energy"] - E) / abs(E), rel(g["forces"], F), rel(g["dvdl"], dv))
+    assert rel(g["forces"], F) <= 2e-4
+    assert rel(g["dvdl"], dv) <= 2e-4
+
+
+def test_potential_output_matches_oracle():
+    s = small_periodic(seed=34)
+    qt, _ = hi.scaled_charges(s.n_atoms, s.q, s.sites)
+    from oracle import ewald
+    phi, _ = ewald.field(s.x, qt, s.box)
+    g = gpu_eval(s, 64, 12, 2, potential=True)
+    assert rel(g["potential"], hi.KE_DEFAULT * phi) <= 1e-5
+
+
+def test_bitwise_deterministic():
+    import paper_2410_01754_amd as pkg
+    s = small_periodic(seed=35)
+    m = pkg.from_system(s, precision=32, order=8, depth=2)
+    a = m.eval(s.x)
+    b = m.eval(s.x)
+    m.close()
+    assert a["energy"] == b["energy"]
+    assert np.array_equal(a["forces"], b["forces"]) and np.array_equal(a["dvdl"], b["dvdl"])
+
+
+# ------------------------------------------------------------------ config 1 (golden oracle values)
+
+def _golden(k):
+    path = os.path.join(HERE, "golden", f"config{k}_oracle.npz")
+    if not os.path.exists(path):
+        pytest.skip(f"{path} not generated")
+    return np.load(path)
+
+
+@pytest.mark.parametrize("prec,order,tol", [
+    (32, 8, 2e-4), (64, 8, 2e-4), (64, 16, 1e-6),
+    pytest.param(32, 16, 1e-6, marks=pytest.mark.xfail(
+        reason="float32 rounding floor (~5e-6 in F, ~1e-5 in dV/dlambda-tilde) lies above 1e-6", strict=False)),
+])
+def test_config1(prec, order, tol):
+    gd = _golden(1)
+    s = make_config(1)
+    g = gpu_eval(s, prec, order, 4)
+    idx = gd["idx"]
+    ef, ed = rel(g["forces"][idx], gd["forces"]), rel(g["dvdl"], gd["dvdl"])
+    ee = abs(g["energy"] - gd["energy"][0]) / abs(gd["energy"][0])
+    print(f"config1 prec={prec} p={order}: E {ee:.3e} F {ef:.3e} dVdl {ed:.3e}")
+    assert ef <= tol and ed <= tol and ee <= tol
+
+
+def test_config2_full_size_sampled():
+    """Paper-scale system (1,004,296 atoms, 512 sites), float32, p = 8, depth 5,
+    against oracle values at every site atom and 4,000 sampled atoms."""
+    gd = _golden(2)
+    s = make_config(2)
+    g = gpu_eval(s, 32, 8, 5)
+    idx = gd["idx"]
+    ef, ed = rel(g["forces"][idx], gd["forces"]), rel(g["dvdl"], gd["dvdl"])
+    ee = abs(g["energy"] - gd["energy"][0]) / abs(gd["energy"][0])
+    print(f"config2 fp32 p=8: E {ee:.3e} F {ef:.3e} dVdl {ed:.3e}")
+    assert ef <= 2e-4 and ed <= 2e-4 and ee <= 2e-4
