@@ -80,7 +80,7 @@ def cpu_baseline(full_n: int):
     from synth import make_system
     cores = os.cpu_count() or 1
     pts = []
-    for edge in (4.0, 5.5):
+    for edge in (6.0, 8.5):
         nw = int(round(33.4 * edge ** 3))
         ns = max(1, int(round(3 * nw / 1960)))
         s = make_system(nw, edge, True, [8] * ns, [2] * ns, total_step=1.0, depth=3, seed=7)
