@@ -14,7 +14,9 @@ OUT = os.path.join(HERE, "libmahi.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 # Packed float32 VALU instructions are disabled for all device code.
-DEVICE_FLAGS = ["--offload-arch=gfx950", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
+DEVICE_FLAGS = ["--offload-arch=gfx950", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+                # matrix-core accumulators in architectural VGPRs (no AGPR copies around each MFMA)
+                "-mllvm", "-amdgpu-mfma-vgpr-form=true"]
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-result"]
 
 

@@ -575,6 +575,182 @@ __global__ void __launch_bounds__(256) k_m2l(const T *__restrict__ M, T *__restr
   }
 }
 
+// ---------------------------------------------------------------------------
+// Generic matrix-core translation: M2L, M2M and L2L as gathered GEMMs.
+//   Y[target] (+)= sum_{op} T_{op} * X[source(target, op)]
+// A block owns 64 targets of one parity class at one level and a group of
+// output row tiles (one tile per wave, 4 waves).  For each (op, k-chunk) step
+// every wave holds its operator slice in registers (prefetched one step
+// ahead) and the 64 gathered source vectors sit in a double-buffered LDS
+// tile, so one barrier per step suffices and global latency overlaps the
+// matrix-core work of the previous step.
+//   M2L: level l, 8 classes, 189 ops per class (offset lists), overwrite.
+//   M2M: parent level l, 1 class, 8 ops (children), overwrite.
+//   L2L: child level l, 8 classes, 1 op per class (the parent), accumulate.
+// ---------------------------------------------------------------------------
+enum { XL_M2L = 0, XL_M2M = 1, XL_L2L = 2 };
+
+template <class T>
+struct XChunk;
+template <>
+struct XChunk<float> {
+  static constexpr int KC = 84;  // k values per chunk (42 MFMA steps of 2): one chunk up to order 8
+};
+template <>
+struct XChunk<double> {
+  static constexpr int KC = 44;  // 11 MFMA steps of 4
+};
+
+template <class T, int MODE>
+__global__ void __launch_bounds__(256) k_xlate(const T *X, T *Y, const T *__restrict__ Tab,
+                                               const int4 *__restrict__ ops, XArgs a) {
+  using MF = Mfma<T>;
+  constexpr int NCT = 64 / MF::TN;
+  constexpr int KC = XChunk<T>::KC;
+  constexpr int NSTEP = KC / MF::TK;
+  constexpr int NB = KC / 4;  // staged B elements per thread and step: 4 threads per target
+  extern __shared__ unsigned char smem_raw[];
+  T *Bs = reinterpret_cast<T *>(smem_raw);  // [2][KC][kBStride]
+  __shared__ int s_tx[64], s_ty[64], s_tz[64];
+
+  // ---- decode the work item
+  int l, li;
+  if (MODE == XL_M2L) {
+    l = a.lmin;
+    while (l < a.d && (int)blockIdx.x >= a.level_start[l + 1]) ++l;
+    li = blockIdx.x - a.level_start[l];
+  } else {
+    l = a.level;
+    li = blockIdx.x;
+  }
+  const int ncls = MODE == XL_M2M ? 1 : 8;
+  const int64_t ntg = MODE == XL_M2M ? (int64_t(1) << (3 * l)) : (int64_t(1) << (3 * (l - 1)));
+  const int chunks = (int)((ntg + 63) / 64);
+  const int g = li % a.ngroups;
+  const int tq = li / a.ngroups;
+  const int chunk = tq % chunks;
+  const int cls = (tq / chunks) % ncls;
+  const int nl = 1 << l;
+  const int srclev = MODE == XL_M2L ? l : (MODE == XL_M2M ? l + 1 : l - 1);
+  const int64_t xoff = level_offset(srclev), yoff = level_offset(l);
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int rt = g * a.nw + wave;
+  const bool active = wave < a.nw && rt < a.nrt;
+  const int4 *lst = ops + cls * a.nops;
+
+  // gather mapping: thread -> (target column jt, k offset kq)
+  const int jt = threadIdx.x >> 2, kq = threadIdx.x & 3;
+  const int64_t Pt = (int64_t)chunk * 64 + jt;
+  int tx = -1, ty = -1, tz = -1;
+  if (Pt < ntg) {
+    if (MODE == XL_M2L) unmorton((uint32_t)(8 * Pt + cls), tx, ty, tz);
+    else tx = ty = tz = 0;
+  }
+
+  const int nkc = (a.KK + KC - 1) / KC;
+  const int nsteps_total = a.nops * nkc;
+  T breg[NB];
+  T areg[NSTEP];
+
+  auto load_b = [&](int step) {
+    const int vi = step / nkc, k0 = (step % nkc) * KC;
+    const int4 v = lst[vi];
+    int64_t sb = -1;
+    if (tx >= 0) {
+      if (MODE == XL_M2M) {
+        sb = 8 * Pt + v.w;
+      } else if (MODE == XL_L2L) {
+        sb = Pt;
+      } else {
+        int sx = tx - v.x, sy = ty - v.y, sz = tz - v.z;
+        bool ok = true;
+        if (a.periodic) {
+          sx = (sx + 4 * nl) & (nl - 1);
+          sy = (sy + 4 * nl) & (nl - 1);
+          sz = (sz + 4 * nl) & (nl - 1);
+        } else {
+          ok = (unsigned)sx < (unsigned)nl && (unsigned)sy < (unsigned)nl && (unsigned)sz < (unsigned)nl;
+        }
+        if (ok) sb = (int64_t)morton(sx, sy, sz);
+      }
+    }
+    const T *src = X + (xoff + (sb < 0 ? 0 : sb)) * a.K + k0;
+    const int kmax = sb < 0 ? 0 : a.K - k0;
+#pragma unroll
+    for (int r = 0; r < NB; ++r) {
+      const int kk = kq + 4 * r;
+      breg[r] = kk < kmax ? src[kk] : T(0);
+    }
+  };
+  auto a_ptr = [&](int step) {
+    const int vi = step / nkc, k0 = (step % nkc) * KC;
+    const int4 v = lst[vi];
+    return Tab + ((int64_t)v.w * a.KK + k0) * a.RP + rt * MF::TM + MF::a_row(lane) +
+           (int64_t)MF::a_k(lane) * a.RP;
+  };
+  auto a_count = [&](int step) { return min(KC, a.KK - (step % nkc) * KC); };
+  auto store_b = [&](int buf) {
+    T *B = Bs + buf * KC * kBStride;
+#pragma unroll
+    for (int r = 0; r < NB; ++r) B[(kq + 4 * r) * kBStride + jt] = breg[r];
+  };
+
+  typename MF::acc_t acc[NCT];
+#pragma unroll
+  for (int c = 0; c < NCT; ++c)
+#pragma unroll
+    for (int r = 0; r < MF::NACC; ++r) acc[c][r] = T(0);
+
+  load_b(0);
+  if (active) {
+    const T *A = a_ptr(0);
+    const int kn = a_count(0);
+#pragma unroll
+    for (int s2 = 0; s2 < NSTEP; ++s2) areg[s2] = (s2 * MF::TK < kn) ? A[(int64_t)s2 * MF::TK * a.RP] : T(0);
+  }
+  for (int step = 0; step < nsteps_total; ++step) {
+    const int buf = step & 1;
+    store_b(buf);
+    __syncthreads();
+    const bool more = step + 1 < nsteps_total;
+    if (more) load_b(step + 1);
+    if (active) {
+      const T *B = Bs + buf * KC * kBStride;
+      const int kn = a_count(step);
+      const T *An = more ? a_ptr(step + 1) : Tab;
+      const int knn = more ? a_count(step + 1) : 0;
+#pragma unroll
+      for (int s2 = 0; s2 < NSTEP; ++s2) {
+        if (s2 * MF::TK < kn) {
+#pragma unroll
+          for (int c = 0; c < NCT; ++c) {
+            const T bf = B[(s2 * MF::TK + MF::b_k(lane)) * kBStride + c * MF::TN + MF::b_col(lane)];
+            acc[c] = MF::mma(areg[s2], bf, acc[c]);
+          }
+        }
+        // reload this slot for the next step right after its use
+        areg[s2] = (s2 * MF::TK < knn) ? An[(int64_t)s2 * MF::TK * a.RP] : T(0);
+      }
+    }
+  }
+  if (active) {
+#pragma unroll
+    for (int c = 0; c < NCT; ++c)
+#pragma unroll
+      for (int r = 0; r < MF::NACC; ++r) {
+        const int row = rt * MF::TM + MF::d_row(lane, r);
+        const int col = c * MF::TN + MF::d_col(lane, r);
+        const int64_t P = (int64_t)chunk * 64 + col;
+        if (row < a.K && P < ntg) {
+          const int64_t tb = MODE == XL_M2M ? P : 8 * P + cls;
+          T *dst = Y + (yoff + tb) * a.K + row;
+          if (MODE == XL_L2L) *dst += acc[c][r];
+          else *dst = acc[c][r];
+        }
+      }
+  }
+}
+
 // Same contraction on the vector ALU (no matrix cores): accumulators of the
 // 64 targets live in LDS, each thread owns (target, row) pairs.  Used for
 // cross-checking the matrix-core path and as a fallback.
@@ -1204,6 +1380,71 @@ void launch_m2l_valu(const T *M, T *L, const T *Tab, const int4 *lists, int p, i
 }
 
 template <class T>
+void xlate_geometry(int p, XArgs &a) {
+  using MF = Mfma<T>;
+  a.K = (p + 1) * (p + 1);
+  a.KK = (a.K + MF::TK - 1) / MF::TK * MF::TK;
+  a.nrt = (a.K + MF::TM - 1) / MF::TM;
+  a.RP = a.nrt * MF::TM;
+  a.ngroups = (a.nrt + 3) / 4;
+  a.nw = (a.nrt + a.ngroups - 1) / a.ngroups;
+}
+
+template <class T>
+static size_t xlate_lds() {
+  return (size_t)2 * XChunk<T>::KC * kBStride * sizeof(T);
+}
+
+template <class T>
+void launch_xlate_m2l(const T *M, T *L, const T *Tab, const int4 *lists, int p, int d, int periodic, hipStream_t st) {
+  XArgs a;
+  xlate_geometry<T>(p, a);
+  a.d = d;
+  a.periodic = periodic;
+  a.lmin = periodic ? 1 : 2;
+  a.nops = kListLen;
+  a.level = 0;
+  int blocks = 0;
+  for (int l = 0; l <= 8; ++l) a.level_start[l] = 0;
+  for (int l = a.lmin; l <= d; ++l) {
+    a.level_start[l] = blocks;
+    const int64_t np = int64_t(1) << (3 * (l - 1));
+    blocks += (int)(8 * ((np + 63) / 64) * a.ngroups);
+  }
+  if (d + 1 <= 8) a.level_start[d + 1] = blocks;
+  if (blocks == 0) return;
+  hipLaunchKernelGGL((k_xlate<T, XL_M2L>), dim3(blocks), dim3(256), xlate_lds<T>(), st, M, L, Tab, lists, a);
+}
+
+template <class T>
+void launch_xlate_m2m(T *M, int lp, const T *Tab, const int4 *ops, int p, hipStream_t st) {
+  XArgs a;
+  xlate_geometry<T>(p, a);
+  a.d = lp + 1;
+  a.periodic = 0;
+  a.lmin = 0;
+  a.nops = 8;
+  a.level = lp;
+  const int64_t np = int64_t(1) << (3 * lp);
+  const int blocks = (int)(((np + 63) / 64) * a.ngroups);
+  hipLaunchKernelGGL((k_xlate<T, XL_M2M>), dim3(blocks), dim3(256), xlate_lds<T>(), st, M, M, Tab, ops, a);
+}
+
+template <class T>
+void launch_xlate_l2l(T *L, int lc, const T *Tab, const int4 *ops, int p, hipStream_t st) {
+  XArgs a;
+  xlate_geometry<T>(p, a);
+  a.d = lc;
+  a.periodic = 0;
+  a.lmin = 0;
+  a.nops = 1;
+  a.level = lc;
+  const int64_t np = int64_t(1) << (3 * (lc - 1));
+  const int blocks = (int)(8 * ((np + 63) / 64) * a.ngroups);
+  hipLaunchKernelGGL((k_xlate<T, XL_L2L>), dim3(blocks), dim3(256), xlate_lds<T>(), st, L, L, Tab, ops, a);
+}
+
+template <class T>
 void launch_mfma_probe(const T *A, const T *B, T *C, int rows, int kk, hipStream_t st) {
   using MF = Mfma<T>;
   hipLaunchKernelGGL(k_mfma_probe<T>, dim3(1), dim3(64 * (rows / MF::TM)), 0, st, A, B, C, rows, kk);
@@ -1265,7 +1506,10 @@ void launch_finalize(const double *epart, int nb, const double *dE_site, int ns,
   template void launch_m2l<T>(const T *, T *, const T *, const int4 *, int, int, int, hipStream_t);                 \
   template void m2l_table_layout<T>(int, int &, int &);                                                               \
   template void launch_mfma_probe<T>(const T *, const T *, T *, int, int, hipStream_t);                              \
-  template void launch_m2l_valu<T>(const T *, T *, const T *, const int4 *, int, int, int, hipStream_t);                              \
+  template void launch_m2l_valu<T>(const T *, T *, const T *, const int4 *, int, int, int, hipStream_t);       \
+  template void launch_xlate_m2l<T>(const T *, T *, const T *, const int4 *, int, int, int, hipStream_t);      \
+  template void launch_xlate_m2m<T>(T *, int, const T *, const int4 *, int, hipStream_t);                      \
+  template void launch_xlate_l2l<T>(T *, int, const T *, const int4 *, int, hipStream_t);                              \
   template int p2p_blocks<T>(int);                                                                                   \
   template void launch_p2p<T>(const Atom4<T> *, const int *, const int *, const T *, const Geom *, int, int, int,    \
                               double, T *, T *, T *, double *, hipStream_t);                                         \

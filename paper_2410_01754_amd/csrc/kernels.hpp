@@ -12,6 +12,12 @@ struct M2LArgs {
   int level_start[9];
 };
 
+struct XArgs {
+  int K, KK, RP, nrt, nw, ngroups;
+  int d, lmin, periodic, nops, level;
+  int level_start[9];
+};
+
 struct P2PArgs {
   int d, periodic, p, K, cap;
   double ke;
@@ -51,6 +57,10 @@ template <class T>
 void launch_m2l(const T *M, T *L, const T *Tab, const int4 *lists, int p, int d, int periodic, hipStream_t st);
 template <class T>
 void launch_m2l_valu(const T *M, T *L, const T *Tab, const int4 *lists, int p, int d, int periodic, hipStream_t st);
+template <class T>
+void launch_xlate_m2l(const T *M, T *L, const T *Tab, const int4 *lists, int p, int d, int periodic, hipStream_t st);
+template <class T> void launch_xlate_m2m(T *M, int lp, const T *Tab, const int4 *ops, int p, hipStream_t st);
+template <class T> void launch_xlate_l2l(T *L, int lc, const T *Tab, const int4 *ops, int p, hipStream_t st);
 template <class T> void launch_mfma_probe(const T *A, const T *B, T *C, int rows, int kk, hipStream_t st);
 template <class T> int p2p_blocks(int d);
 template <class T>
