@@ -35,6 +35,9 @@ struct mahi_ctx {
   int periodic = 1;
   double edge = 0.0;
   int p = 8, d = 0, prec = 32;
+  int KS = 0;      // stride of one box's coefficients in the multipole/local arrays (>= (p+1)^2, zero padded)
+  int n_cu = 256;  // compute units of the device
+  M2LPlan plan32{};  // float32 M2L decomposition
   double ke = kDefaultKe;
   hipStream_t stream = nullptr;
   bool own_stream = false;
@@ -46,6 +49,7 @@ struct mahi_ctx {
 
   // device buffers (element type T = float or double for the FMM arrays)
   void *xyz = nullptr, *qt = nullptr, *F = nullptr, *pot = nullptr, *phi_sorted = nullptr;
+  void *part = nullptr;  // float32 M2L partial locals, one array per operator range
   void *Mc = nullptr, *Lc = nullptr, *m2l = nullptr, *m2m = nullptr, *l2l = nullptr, *sorted = nullptr;
   double *LamT = nullptr, *qds = nullptr, *epart = nullptr, *dE_site = nullptr, *dvdl = nullptr, *E = nullptr;
   double *bbox = nullptr, *lam = nullptr, *fq = nullptr;
@@ -133,6 +137,14 @@ mahi_status setup_device(mahi_ctx *ctx, const std::vector<double> &q_env, const 
   const int64_t N = ctx->N;
   const int nleaf = 1 << (3 * d);
   const int64_t nbox = level_offset(d + 1);
+  const bool f32 = sizeof(T) == sizeof(float);
+  if (f32) {
+    m2l32_plan(p, d, ctx->periodic, ctx->n_cu, ctx->plan32);
+    ctx->KS = ctx->plan32.KS;
+  } else {
+    ctx->KS = K;
+  }
+  const int KS = ctx->KS;
   HIP_TRY(upload_constants(), "constant tables");
   HIP_TRY(ctx->alloc(ctx->xyz, sizeof(T) * 3 * N), "alloc xyz");
   HIP_TRY(ctx->alloc(ctx->qt, sizeof(T) * N), "alloc charges");
@@ -140,9 +152,13 @@ mahi_status setup_device(mahi_ctx *ctx, const std::vector<double> &q_env, const 
   HIP_TRY(ctx->alloc(ctx->pot, sizeof(T) * N), "alloc potential");
   HIP_TRY(ctx->alloc(ctx->phi_sorted, sizeof(T) * N), "alloc potential (sorted)");
   HIP_TRY(ctx->alloc(ctx->sorted, sizeof(Atom4<T>) * N), "alloc sorted atoms");
-  HIP_TRY(ctx->alloc(ctx->Mc, sizeof(T) * nbox * K), "alloc multipoles");
-  HIP_TRY(ctx->alloc(ctx->Lc, sizeof(T) * nbox * K), "alloc locals");
-  HIP_TRY(hipMemset(ctx->Lc, 0, sizeof(T) * nbox * K), "zero locals");
+  // one extra all-zero box row (the source of empty M2L slots); pads stay zero
+  HIP_TRY(ctx->alloc(ctx->Mc, sizeof(T) * (nbox + 1) * KS), "alloc multipoles");
+  HIP_TRY(ctx->alloc(ctx->Lc, sizeof(T) * (nbox + 1) * KS), "alloc locals");
+  HIP_TRY(hipMemset(ctx->Mc, 0, sizeof(T) * (nbox + 1) * KS), "zero multipoles");
+  HIP_TRY(hipMemset(ctx->Lc, 0, sizeof(T) * (nbox + 1) * KS), "zero locals");
+  if (f32 && ctx->plan32.nsplit > 1)
+    HIP_TRY(ctx->alloc(ctx->part, sizeof(T) * ctx->plan32.nsplit * nbox * KS), "alloc M2L partials");
   HIP_TRY(ctx->alloc(ctx->key, sizeof(int) * N), "alloc keys");
   HIP_TRY(ctx->alloc(ctx->tmp, sizeof(int) * N), "alloc scatter");
   HIP_TRY(ctx->alloc(ctx->perm, sizeof(int) * N), "alloc perm");
@@ -194,13 +210,18 @@ mahi_status setup_device(mahi_ctx *ctx, const std::vector<double> &q_env, const 
   }
   const int lmin = ctx->periodic ? 1 : 2;
   if (d >= lmin) {
-    std::vector<T> tab((size_t)kSlots * KK * RP, T(0));
+    // float32: operator-shared layout of k_m2l_f32; float64: [slot][k][row] of k_xlate
+    std::vector<T> tab(f32 ? m2l32_table_size(ctx->plan32, kSlots) : (size_t)kSlots * KK * RP, T(0));
     std::vector<double> Tv((size_t)K * K);
     for (int slot = 0; slot < kSlots; ++slot) {
       const int vx = slot / 49 - 3, vy = (slot / 7) % 7 - 3, vz = slot % 7 - 3;
       if (std::max(std::abs(vx), std::max(std::abs(vy), std::abs(vz))) <= 1) continue;
       const double v[3] = {double(vx), double(vy), double(vz)};
       m2l_matrix(p, v, Tv.data());
+      if (f32) {
+        m2l32_table(ctx->plan32, slot, Tv.data(), reinterpret_cast<float *>(tab.data()));
+        continue;
+      }
       T *dst = tab.data() + (size_t)slot * KK * RP;
       for (int r = 0; r < K; ++r)
         for (int c = 0; c < K; ++c) dst[(size_t)c * RP + r] = (T)Tv[(size_t)r * K + c];
@@ -262,7 +283,7 @@ template <class T>
 mahi_status eval_impl(mahi_ctx *ctx, const mahi_eval_args *a) {
   const bool dev = (a->flags & MAHI_DEVICE_IO) != 0;
   const int64_t N = ctx->N;
-  const int p = ctx->p, d = ctx->d, K = ncoef(p), nleaf = 1 << (3 * d);
+  const int p = ctx->p, d = ctx->d, KS = ctx->KS, nleaf = 1 << (3 * d);
   hipStream_t st = ctx->stream;
   HIP_TRY(hipSetDevice(ctx->device), "set device");
   const T *xyz = static_cast<const T *>(a->xyz);
@@ -283,22 +304,28 @@ mahi_status eval_impl(mahi_ctx *ctx, const mahi_eval_args *a) {
                  static_cast<Atom4<T> *>(ctx->sorted)};
   launch_tree<T>(xyz, static_cast<const T *>(ctx->qt), N, ctx->geom, d, ctx->periodic, tb, st);
   ctx->mark(1);
-  launch_p2m<T>(tb.sorted, ctx->start, nleaf, p, Mc + level_offset(d) * K, ctx->periodic ? ctx->qds : nullptr, ctx->geom,
-                d, st);
+  launch_p2m<T>(tb.sorted, ctx->start, nleaf, p, KS, Mc + level_offset(d) * KS, ctx->periodic ? ctx->qds : nullptr,
+                ctx->geom, d, st);
   ctx->mark(2);
   const int lmin = ctx->periodic ? 1 : 2;
   const int mlow = ctx->periodic ? 0 : 2;
-  for (int l = d - 1; l >= mlow; --l) launch_xlate_m2m<T>(Mc, l, static_cast<const T *>(ctx->m2m), ctx->child_ops, p, st);
+  for (int l = d - 1; l >= mlow; --l)
+    launch_xlate_m2m<T>(Mc, l, static_cast<const T *>(ctx->m2m), ctx->child_ops, p, KS, st);
   ctx->mark(3);
-  if (ctx->periodic) launch_lattice<T>(Mc, Lc, ctx->LamT, K, ctx->qds, nleaf, ctx->geom, st);
+  if (ctx->periodic) launch_lattice<T>(Mc, Lc, ctx->LamT, ncoef(p), ctx->qds, nleaf, ctx->geom, st);
   ctx->mark(4);
-  if (d >= lmin)
-    launch_xlate_m2l<T>(Mc, Lc, static_cast<const T *>(ctx->m2l), ctx->lists, p, d, ctx->periodic, st);
+  if (d >= lmin) {
+    if constexpr (sizeof(T) == sizeof(float))
+      launch_m2l_f32(Mc, Lc, static_cast<float *>(ctx->part), static_cast<const float *>(ctx->m2l), ctx->lists,
+                     ctx->plan32, st);
+    else
+      launch_xlate_m2l<T>(Mc, Lc, static_cast<const T *>(ctx->m2l), ctx->lists, p, KS, d, ctx->periodic, st);
+  }
   ctx->mark(5);
   for (int l = ctx->periodic ? 1 : 3; l <= d; ++l)
-    launch_xlate_l2l<T>(Lc, l, static_cast<const T *>(ctx->l2l), ctx->child_ops, p, st);
+    launch_xlate_l2l<T>(Lc, l, static_cast<const T *>(ctx->l2l), ctx->child_ops, p, KS, st);
   ctx->mark(6);
-  launch_p2p<T>(tb.sorted, ctx->start, ctx->perm, Lc + level_offset(d) * K, ctx->geom, d, ctx->periodic, p, ctx->ke,
+  launch_p2p<T>(tb.sorted, ctx->start, ctx->perm, Lc + level_offset(d) * KS, KS, ctx->geom, d, ctx->periodic, p, ctx->ke,
                 static_cast<T *>(ctx->phi_sorted), F, pot, ctx->epart, st);
   ctx->mark(7);
   if (ctx->M > 0) {
@@ -428,6 +455,7 @@ mahi_status mahi_create(mahi_ctx **out, const mahi_box *box, int64_t n_atoms, co
   ctx->prec = opts->precision;
   ctx->ke = opts->coulomb_k > 0 ? opts->coulomb_k : kDefaultKe;
   ctx->device = dev;
+  ctx->n_cu = prop.multiProcessorCount;
   ctx->M = M;
   ctx->nforms = form_off.back();
   ctx->nsite_atoms = (int)site_atoms.size();
@@ -559,7 +587,7 @@ mahi_status mahi_profile_end(mahi_ctx *ctx, double *stage_ms, int *n_evals) {
 mahi_status mahi_debug_copy(mahi_ctx *ctx, int which, void *host_out, int64_t count) {
   if (!ctx || !host_out || count < 0) return MAHI_EINVAL;
   const size_t el = ctx->prec == 32 ? sizeof(float) : sizeof(double);
-  const int K = ncoef(ctx->p);
+  const int K = ncoef(ctx->p), KS = ctx->KS;
   const int64_t nbox = level_offset(ctx->d + 1);
   const void *src = nullptr;
   size_t bytes = 0;
@@ -575,6 +603,18 @@ mahi_status mahi_debug_copy(mahi_ctx *ctx, int which, void *host_out, int64_t co
   if (want > bytes) return ctx->fail(MAHI_ERANGE, "count exceeds the buffer");
   HIP_TRY(hipSetDevice(ctx->device), "set device");
   HIP_TRY(hipStreamSynchronize(ctx->stream), "synchronise");
+  if ((which == 0 || which == 1) && KS != K) {
+    // boxes are stored with stride KS: copy whole rows, then drop the padding
+    const int64_t nb = (count + K - 1) / K;
+    std::vector<unsigned char> rows((size_t)nb * KS * el);
+    HIP_TRY(hipMemcpy(rows.data(), src, rows.size(), hipMemcpyDeviceToHost), "copy");
+    unsigned char *out = static_cast<unsigned char *>(host_out);
+    for (int64_t i = 0; i < count; ++i) {
+      const int64_t b = i / K, k = i - b * K;
+      std::memcpy(out + (size_t)i * el, rows.data() + ((size_t)b * KS + k) * el, el);
+    }
+    return MAHI_OK;
+  }
   HIP_TRY(hipMemcpy(host_out, src, want, hipMemcpyDeviceToHost), "copy");
   return MAHI_OK;
 }

@@ -11,6 +11,9 @@
 // float32 path never subtracts large absolute coordinates.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+#include <cmath>
+
 #include "device_common.hpp"
 #include "kernels.hpp"
 
@@ -276,7 +279,7 @@ __global__ void __launch_bounds__(256) k_leafsort(const int *__restrict__ tmp, c
 // ---------------------------------------------------------------------------
 template <class T>
 __global__ void __launch_bounds__(64) k_p2m(const Atom4<T> *__restrict__ sorted, const int *__restrict__ start,
-                                            int p, int K, int chunk, T *__restrict__ Mleaf, double *__restrict__ qds,
+                                            int p, int K, int KS, int chunk, T *__restrict__ Mleaf, double *__restrict__ qds,
                                             const Geom *__restrict__ gp, int d) {
   extern __shared__ unsigned char smem_raw[];
   T *rows = reinterpret_cast<T *>(smem_raw);
@@ -309,7 +312,7 @@ __global__ void __launch_bounds__(64) k_p2m(const Atom4<T> *__restrict__ sorted,
 #pragma unroll
   for (int i = 0; i < kMaxPer; ++i) {
     const int k = lane + 64 * i;
-    if (k < K) Mleaf[(int64_t)leaf * K + k] = acc[i];
+    if (k < K) Mleaf[(int64_t)leaf * KS + k] = acc[i];
   }
   if (qds) {
     const Geom g = *gp;
@@ -334,69 +337,6 @@ __global__ void __launch_bounds__(64) k_p2m(const Atom4<T> *__restrict__ sorted,
       for (int k = 0; k < 5; ++k) v[k] += __shfl_xor(v[k], off);
     if (lane == 0)
       for (int k = 0; k < 5; ++k) qds[(int64_t)leaf * 5 + k] = v[k];
-  }
-}
-
-// ---------------------------------------------------------------------------
-// M2M and L2L: dense per-child translations, PB parents per block
-// ---------------------------------------------------------------------------
-template <class T>
-__global__ void __launch_bounds__(128) k_m2m(T *__restrict__ M, int lp, int K, const T *__restrict__ Tm, int PB) {
-  extern __shared__ unsigned char smem_raw[];
-  T *ch = reinterpret_cast<T *>(smem_raw);  // [PB][8][K]
-  const int64_t nparent = int64_t(1) << (3 * lp);
-  const int64_t p0 = (int64_t)blockIdx.x * PB;
-  const int64_t offc = level_offset(lp + 1) * K, offp = level_offset(lp) * K;  // element offsets
-  for (int e = threadIdx.x; e < PB * 8 * K; e += blockDim.x) {
-    const int pb = e / (8 * K), rem = e % (8 * K);
-    const int64_t P = p0 + pb;
-    ch[e] = (P < nparent) ? M[offc + 8 * P * K + rem] : T(0);
-  }
-  __syncthreads();
-  for (int r = threadIdx.x; r < K; r += blockDim.x) {
-    T acc[8];
-#pragma unroll
-    for (int pb = 0; pb < 8; ++pb) acc[pb] = T(0);
-    for (int s = 0; s < 8; ++s)
-      for (int c = 0; c < K; ++c) {
-        const T t = Tm[((int64_t)s * K + c) * K + r];
-#pragma unroll
-        for (int pb = 0; pb < 8; ++pb)
-          if (pb < PB) acc[pb] += t * ch[(pb * 8 + s) * K + c];
-      }
-#pragma unroll
-    for (int pb = 0; pb < 8; ++pb)
-      if (pb < PB && p0 + pb < nparent) M[offp + (p0 + pb) * K + r] = acc[pb];
-  }
-}
-
-template <class T>
-__global__ void __launch_bounds__(128) k_l2l(T *__restrict__ L, int lc, int K, const T *__restrict__ Tl, int PB) {
-  extern __shared__ unsigned char smem_raw[];
-  T *par = reinterpret_cast<T *>(smem_raw);  // [PB][K]
-  const int64_t nparent = int64_t(1) << (3 * (lc - 1));
-  const int64_t p0 = (int64_t)blockIdx.x * PB;
-  const int64_t offc = level_offset(lc) * K, offp = level_offset(lc - 1) * K;  // element offsets
-  for (int e = threadIdx.x; e < PB * K; e += blockDim.x) {
-    const int pb = e / K, c = e % K;
-    par[e] = (p0 + pb < nparent) ? L[offp + (p0 + pb) * K + c] : T(0);
-  }
-  __syncthreads();
-  for (int r = threadIdx.x; r < K; r += blockDim.x) {
-    for (int s = 0; s < 8; ++s) {
-      T acc[8];
-#pragma unroll
-      for (int pb = 0; pb < 8; ++pb) acc[pb] = T(0);
-      for (int c = 0; c < K; ++c) {
-        const T t = Tl[((int64_t)s * K + c) * K + r];
-#pragma unroll
-        for (int pb = 0; pb < 8; ++pb)
-          if (pb < PB) acc[pb] += t * par[pb * K + c];
-      }
-#pragma unroll
-      for (int pb = 0; pb < 8; ++pb)
-        if (pb < PB && p0 + pb < nparent) L[offc + (8 * (p0 + pb) + s) * K + r] += acc[pb];
-    }
   }
 }
 
@@ -478,103 +418,6 @@ struct Mfma<double> {
 
 constexpr int kBStride = 65;  // LDS row stride of the staged B operand (64 targets + 1 pad)
 
-template <class T>
-__global__ void __launch_bounds__(256) k_m2l(const T *__restrict__ M, T *__restrict__ L, const T *__restrict__ Tab,
-                                             const int4 *__restrict__ lists, M2LArgs a) {
-  using MF = Mfma<T>;
-  constexpr int NCT = 64 / MF::TN;
-  extern __shared__ unsigned char smem_raw[];
-  T *Bs = reinterpret_cast<T *>(smem_raw);  // [kc][kBStride]
-  __shared__ int s_tx[64], s_ty[64], s_tz[64];
-  __shared__ int64_t s_src[64];
-
-  int item = blockIdx.x, l = a.lmin;
-  while (l < a.d && item >= a.level_start[l + 1]) ++l;
-  const int li = item - a.level_start[l];
-  const int64_t nparent = int64_t(1) << (3 * (l - 1));
-  const int chunks = (int)((nparent + 63) / 64);
-  const int g = li % a.ngroups;
-  const int tq = li / a.ngroups;
-  const int chunk = tq % chunks;
-  const int cls = tq / chunks;
-  const int nl = 1 << l;
-  const int64_t off = level_offset(l);  // box offset of level l
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int rt = g * a.nw + wave;
-  const bool active = rt < a.nrt;
-
-  if (threadIdx.x < 64) {
-    const int64_t P = (int64_t)chunk * 64 + threadIdx.x;
-    int tx = -1, ty = -1, tz = -1;
-    if (P < nparent) unmorton((uint32_t)(8 * P + cls), tx, ty, tz);
-    s_tx[threadIdx.x] = tx;
-    s_ty[threadIdx.x] = ty;
-    s_tz[threadIdx.x] = tz;
-  }
-
-  typename MF::acc_t acc[NCT];
-#pragma unroll
-  for (int c = 0; c < NCT; ++c)
-#pragma unroll
-    for (int r = 0; r < MF::NACC; ++r) acc[c][r] = T(0);
-
-  const int4 *lst = lists + cls * kListLen;
-  for (int vi = 0; vi < kListLen; ++vi) {
-    const int4 v = lst[vi];
-    __syncthreads();
-    if (threadIdx.x < 64) {
-      const int j = threadIdx.x;
-      int64_t src = -1;
-      if (s_tx[j] >= 0) {
-        int sx = s_tx[j] - v.x, sy = s_ty[j] - v.y, sz = s_tz[j] - v.z;
-        bool ok = true;
-        if (a.periodic) {
-          sx = (sx + 4 * nl) & (nl - 1);
-          sy = (sy + 4 * nl) & (nl - 1);
-          sz = (sz + 4 * nl) & (nl - 1);
-        } else {
-          ok = (unsigned)sx < (unsigned)nl && (unsigned)sy < (unsigned)nl && (unsigned)sz < (unsigned)nl;
-        }
-        if (ok) src = (off + (int64_t)morton(sx, sy, sz)) * a.K;
-      }
-      s_src[j] = src;
-    }
-    for (int k0 = 0; k0 < a.KK; k0 += a.kc) {
-      const int kn = min(a.kc, a.KK - k0);
-      __syncthreads();
-      for (int e = threadIdx.x; e < 64 * kn; e += blockDim.x) {
-        const int j = e / kn, kk = e - j * kn;
-        const int k = k0 + kk;
-        const int64_t src = s_src[j];
-        Bs[kk * kBStride + j] = (src >= 0 && k < a.K) ? M[src + k] : T(0);
-      }
-      __syncthreads();
-      if (active) {
-        const T *A = Tab + ((int64_t)v.w * a.KK + k0) * a.RP + rt * MF::TM;
-        for (int kb = 0; kb < kn; kb += MF::TK) {
-          const T af = A[(int64_t)(kb + MF::a_k(lane)) * a.RP + MF::a_row(lane)];
-#pragma unroll
-          for (int c = 0; c < NCT; ++c) {
-            const T bf = Bs[(kb + MF::b_k(lane)) * kBStride + c * MF::TN + MF::b_col(lane)];
-            acc[c] = MF::mma(af, bf, acc[c]);
-          }
-        }
-      }
-    }
-  }
-  if (active) {
-#pragma unroll
-    for (int c = 0; c < NCT; ++c)
-#pragma unroll
-      for (int r = 0; r < MF::NACC; ++r) {
-        const int row = rt * MF::TM + MF::d_row(lane, r);
-        const int col = c * MF::TN + MF::d_col(lane, r);
-        const int64_t P = (int64_t)chunk * 64 + col;
-        if (row < a.K && P < nparent) L[(off + 8 * P + cls) * a.K + row] = acc[c][r];
-      }
-  }
-}
-
 // ---------------------------------------------------------------------------
 // Generic matrix-core translation: M2L, M2M and L2L as gathered GEMMs.
 //   Y[target] (+)= sum_{op} T_{op} * X[source(target, op)]
@@ -601,17 +444,16 @@ struct XChunk<double> {
   static constexpr int KC = 44;  // 11 MFMA steps of 4
 };
 
-template <class T, int MODE>
-__global__ void __launch_bounds__(256) k_xlate(const T *X, T *Y, const T *__restrict__ Tab,
+template <class T, int MODE, int TPT>
+__global__ void __launch_bounds__(64 * TPT) k_xlate(const T *X, T *Y, const T *__restrict__ Tab,
                                                const int4 *__restrict__ ops, XArgs a) {
   using MF = Mfma<T>;
   constexpr int NCT = 64 / MF::TN;
   constexpr int KC = XChunk<T>::KC;
   constexpr int NSTEP = KC / MF::TK;
-  constexpr int NB = KC / 4;  // staged B elements per thread and step: 4 threads per target
+  constexpr int NB = (KC + TPT - 1) / TPT;  // staged B elements per thread and step (TPT threads per target)
   extern __shared__ unsigned char smem_raw[];
   T *Bs = reinterpret_cast<T *>(smem_raw);  // [2][KC][kBStride]
-  __shared__ int s_tx[64], s_ty[64], s_tz[64];
 
   // ---- decode the work item
   int l, li;
@@ -638,8 +480,8 @@ __global__ void __launch_bounds__(256) k_xlate(const T *X, T *Y, const T *__rest
   const bool active = wave < a.nw && rt < a.nrt;
   const int4 *lst = ops + cls * a.nops;
 
-  // gather mapping: thread -> (target column jt, k offset kq)
-  const int jt = threadIdx.x >> 2, kq = threadIdx.x & 3;
+  // gather mapping: thread -> (target column jt, k offset kq), TPT threads per target
+  const int jt = threadIdx.x / TPT, kq = threadIdx.x - jt * TPT;
   const int64_t Pt = (int64_t)chunk * 64 + jt;
   int tx = -1, ty = -1, tz = -1;
   if (Pt < ntg) {
@@ -647,7 +489,7 @@ __global__ void __launch_bounds__(256) k_xlate(const T *X, T *Y, const T *__rest
     else tx = ty = tz = 0;
   }
 
-  const int nkc = (a.KK + KC - 1) / KC;
+  const int nkc = a.KK / KC;
   const int nsteps_total = a.nops * nkc;
   T breg[NB];
   T areg[NSTEP];
@@ -674,12 +516,12 @@ __global__ void __launch_bounds__(256) k_xlate(const T *X, T *Y, const T *__rest
         if (ok) sb = (int64_t)morton(sx, sy, sz);
       }
     }
-    const T *src = X + (xoff + (sb < 0 ? 0 : sb)) * a.K + k0;
+    const T *src = X + (xoff + (sb < 0 ? 0 : sb)) * a.KS + k0;
     const int kmax = sb < 0 ? 0 : a.K - k0;
 #pragma unroll
     for (int r = 0; r < NB; ++r) {
-      const int kk = kq + 4 * r;
-      breg[r] = kk < kmax ? src[kk] : T(0);
+      const int kk = kq + TPT * r;
+      breg[r] = (kk < kmax && kk < KC) ? src[kk] : T(0);
     }
   };
   auto a_ptr = [&](int step) {
@@ -688,11 +530,13 @@ __global__ void __launch_bounds__(256) k_xlate(const T *X, T *Y, const T *__rest
     return Tab + ((int64_t)v.w * a.KK + k0) * a.RP + rt * MF::TM + MF::a_row(lane) +
            (int64_t)MF::a_k(lane) * a.RP;
   };
-  auto a_count = [&](int step) { return min(KC, a.KK - (step % nkc) * KC); };
   auto store_b = [&](int buf) {
     T *B = Bs + buf * KC * kBStride;
 #pragma unroll
-    for (int r = 0; r < NB; ++r) B[(kq + 4 * r) * kBStride + jt] = breg[r];
+    for (int r = 0; r < NB; ++r) {
+      const int kk = kq + TPT * r;
+      if (kk < KC) B[kk * kBStride + jt] = breg[r];
+    }
   };
 
   typename MF::acc_t acc[NCT];
@@ -704,9 +548,8 @@ __global__ void __launch_bounds__(256) k_xlate(const T *X, T *Y, const T *__rest
   load_b(0);
   if (active) {
     const T *A = a_ptr(0);
-    const int kn = a_count(0);
 #pragma unroll
-    for (int s2 = 0; s2 < NSTEP; ++s2) areg[s2] = (s2 * MF::TK < kn) ? A[(int64_t)s2 * MF::TK * a.RP] : T(0);
+    for (int s2 = 0; s2 < NSTEP; ++s2) areg[s2] = A[(int64_t)s2 * MF::TK * a.RP];
   }
   for (int step = 0; step < nsteps_total; ++step) {
     const int buf = step & 1;
@@ -715,21 +558,16 @@ __global__ void __launch_bounds__(256) k_xlate(const T *X, T *Y, const T *__rest
     const bool more = step + 1 < nsteps_total;
     if (more) load_b(step + 1);
     if (active) {
-      const T *B = Bs + buf * KC * kBStride;
-      const int kn = a_count(step);
-      const T *An = more ? a_ptr(step + 1) : Tab;
-      const int knn = more ? a_count(step + 1) : 0;
+      // The chunk is full (zero-padded table rows and staged B rows), so the
+      // k loop has no bounds tests and the LDS reads can run ahead of the MFMAs.
+      const T *Bl = Bs + buf * KC * kBStride + MF::b_k(lane) * kBStride + MF::b_col(lane);
+      const T *An = more ? a_ptr(step + 1) : a_ptr(step);
 #pragma unroll
       for (int s2 = 0; s2 < NSTEP; ++s2) {
-        if (s2 * MF::TK < kn) {
 #pragma unroll
-          for (int c = 0; c < NCT; ++c) {
-            const T bf = B[(s2 * MF::TK + MF::b_k(lane)) * kBStride + c * MF::TN + MF::b_col(lane)];
-            acc[c] = MF::mma(areg[s2], bf, acc[c]);
-          }
-        }
+        for (int c = 0; c < NCT; ++c) acc[c] = MF::mma(areg[s2], Bl[s2 * MF::TK * kBStride + c * MF::TN], acc[c]);
         // reload this slot for the next step right after its use
-        areg[s2] = (s2 * MF::TK < knn) ? An[(int64_t)s2 * MF::TK * a.RP] : T(0);
+        areg[s2] = An[(int64_t)s2 * MF::TK * a.RP];
       }
     }
   }
@@ -743,7 +581,7 @@ __global__ void __launch_bounds__(256) k_xlate(const T *X, T *Y, const T *__rest
         const int64_t P = (int64_t)chunk * 64 + col;
         if (row < a.K && P < ntg) {
           const int64_t tb = MODE == XL_M2M ? P : 8 * P + cls;
-          T *dst = Y + (yoff + tb) * a.K + row;
+          T *dst = Y + (yoff + tb) * a.KS + row;
           if (MODE == XL_L2L) *dst += acc[c][r];
           else *dst = acc[c][r];
         }
@@ -751,83 +589,176 @@ __global__ void __launch_bounds__(256) k_xlate(const T *X, T *Y, const T *__rest
   }
 }
 
-// Same contraction on the vector ALU (no matrix cores): accumulators of the
-// 64 targets live in LDS, each thread owns (target, row) pairs.  Used for
-// cross-checking the matrix-core path and as a fallback.
-template <class T>
-__global__ void __launch_bounds__(256) k_m2l_valu(const T *__restrict__ M, T *__restrict__ L,
-                                                  const T *__restrict__ Tab, const int4 *__restrict__ lists,
-                                                  M2LArgs a) {
-  extern __shared__ unsigned char smem_raw[];
-  T *Bs = reinterpret_cast<T *>(smem_raw);  // [K][64]
-  T *Acc = Bs + (size_t)a.K * 64;           // [64][K]
-  __shared__ int s_tx[64], s_ty[64], s_tz[64];
-  __shared__ int64_t s_src[64];
-  int item = blockIdx.x, l = a.lmin;
-  while (l < a.d && item >= a.level_start[l + 1]) ++l;
-  const int li = item - a.level_start[l];
-  const int64_t nparent = int64_t(1) << (3 * (l - 1));
-  const int chunks = (int)((nparent + 63) / 64);
-  const int chunk = li % chunks;
-  const int cls = li / chunks;
+// ---------------------------------------------------------------------------
+// M2L in float32 on the matrix cores, operator shared through LDS.
+// Work item: (level, parity class, 128 consecutive targets of that class, row
+// group of 96 output rows, range of operators of the 189-entry list).  A block
+// has 4 waves; wave w owns 32 targets (one 32-column MFMA tile) and the 3 row
+// tiles of the group.  For every (operator v, k chunk):
+//   * the block stages T_v (96 rows x KC) once in LDS (double buffered);
+//   * each wave holds its 32 gathered source multipoles in registers, loaded
+//     as float2 from the padded multipole rows (stride KS, a multiple of 4);
+//   * each wave runs 3 x KC/2 MFMA 32x32x2 into 3 accumulator tiles.
+// In k-step s the lanes of half h (lane >> 5) contract k = 4(s/2) + 2h + s%2:
+// the k index of one MFMA is internal to the instruction, so any pairing of
+// the two halves works as long as A and B agree.  The operator rows are
+// stored pre-permuted (LDS row 2s + h holds that k), and each lane's B values
+// are pairs of consecutive k.  Several operator ranges of one target tile
+// write separate partial sums that k_m2l_reduce adds in a fixed order.
+// ---------------------------------------------------------------------------
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+
+template <int KC>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2)))
+k_m2l_f32(const float *__restrict__ M, float *__restrict__ Out, const float *__restrict__ Tab,
+          const int4 *__restrict__ lists, M2LPlan a) {
+  constexpr int RG = kM2LRowGroup;  // rows per group (3 tiles of 32)
+  constexpr int NS = KC / 2;        // MFMA k-steps per chunk
+  constexpr int NQ = KC / 4;        // float2 loads per lane per chunk
+  constexpr int AV = KC * RG / 4;   // float4 elements of one staged operator chunk
+  constexpr int AR = (AV + 255) / 256;
+  __shared__ float As[2][KC * RG];
+
+  // ---- work item (blocks of one XCD take consecutive items)
+  const int nitems = a.nsplit * a.ngroups * a.ntiles;
+  const int bid = blockIdx.x;
+  const int item = (bid & 7) * (nitems >> 3) + (bid >> 3);
+  const int tile = item % a.ntiles;
+  const int rest = item / a.ntiles;
+  const int grp = rest % a.ngroups;
+  const int split = rest / a.ngroups;
+  int l = a.lmin;
+  while (l < a.d && tile >= a.tiles_start[l + 1]) ++l;
+  const int tl = tile - a.tiles_start[l];
+  const int cls = tl & 7, chunk = tl >> 3;
+  const int o0 = split * kListLen / a.nsplit, o1 = (split + 1) * kListLen / a.nsplit;
+  const int nit = (o1 - o0) * a.nkc;
+
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int h = lane >> 5, j = lane & 31;
   const int nl = 1 << l;
+  const int64_t ntg = int64_t(1) << (3 * (l - 1));
+  const int64_t P = (int64_t)chunk * kM2LTile + wave * 32 + j;
+  const bool valid = P < ntg;
+  int tx = 0, ty = 0, tz = 0;
+  if (valid) unmorton((uint32_t)(8 * P + cls), tx, ty, tz);
   const int64_t off = level_offset(l);
-  const int K = a.K;
-  if (threadIdx.x < 64) {
-    const int64_t P = (int64_t)chunk * 64 + threadIdx.x;
-    int tx = -1, ty = -1, tz = -1;
-    if (P < nparent) unmorton((uint32_t)(8 * P + cls), tx, ty, tz);
-    s_tx[threadIdx.x] = tx;
-    s_ty[threadIdx.x] = ty;
-    s_tz[threadIdx.x] = tz;
-  }
-  for (int e = threadIdx.x; e < 64 * K; e += blockDim.x) Acc[e] = T(0);
   const int4 *lst = lists + cls * kListLen;
-  for (int vi = 0; vi < kListLen; ++vi) {
-    const int4 v = lst[vi];
-    __syncthreads();
-    if (threadIdx.x < 64) {
-      const int j = threadIdx.x;
-      int64_t src = -1;
-      if (s_tx[j] >= 0) {
-        int sx = s_tx[j] - v.x, sy = s_ty[j] - v.y, sz = s_tz[j] - v.z;
-        bool ok = true;
-        if (a.periodic) {
-          sx = (sx + 4 * nl) & (nl - 1);
-          sy = (sy + 4 * nl) & (nl - 1);
-          sz = (sz + 4 * nl) & (nl - 1);
-        } else {
-          ok = (unsigned)sx < (unsigned)nl && (unsigned)sy < (unsigned)nl && (unsigned)sz < (unsigned)nl;
-        }
-        if (ok) src = (off + (int64_t)morton(sx, sy, sz)) * K;
-      }
-      s_src[j] = src;
+
+  // source row (in boxes) of operator iteration `it`, or the all-zero row
+  auto src_row = [&](int it) -> int64_t {
+    const int4 v = lst[o0 + it / a.nkc];
+    int sx = tx - v.x, sy = ty - v.y, sz = tz - v.z;
+    bool ok = valid;
+    if (a.periodic) {
+      sx = (sx + 4 * nl) & (nl - 1);
+      sy = (sy + 4 * nl) & (nl - 1);
+      sz = (sz + 4 * nl) & (nl - 1);
+    } else {
+      ok = ok && (unsigned)sx < (unsigned)nl && (unsigned)sy < (unsigned)nl && (unsigned)sz < (unsigned)nl;
     }
-    __syncthreads();
-    for (int e = threadIdx.x; e < 64 * K; e += blockDim.x) {
-      const int j = e / K, k = e - j * K;
-      const int64_t src = s_src[j];
-      Bs[k * 64 + j] = src >= 0 ? M[src + k] : T(0);
+    return ok ? off + (int64_t)morton(sx, sy, sz) : a.zbox;
+  };
+  auto load_b = [&](int it, float *b) {
+    const int c = it % a.nkc;
+    const float2 *q = reinterpret_cast<const float2 *>(M + src_row(it) * a.KS + c * KC + 2 * h);
+#pragma unroll
+    for (int i = 0; i < NQ; ++i) {
+      const float2 v = q[2 * i];
+      b[2 * i] = v.x;
+      b[2 * i + 1] = v.y;
     }
-    __syncthreads();
-    const T *A = Tab + (int64_t)v.w * a.KK * a.RP;
-    for (int e = threadIdx.x; e < 64 * K; e += blockDim.x) {
-      const int row = e / 64, j = e & 63;
-      T acc = Acc[j * K + row];
-      for (int k = 0; k < K; ++k) acc += A[(int64_t)k * a.RP + row] * Bs[k * 64 + j];
-      Acc[j * K + row] = acc;
+  };
+  auto a_src = [&](int it) {
+    const int4 v = lst[o0 + it / a.nkc];
+    const int c = it % a.nkc;
+    return reinterpret_cast<const floatx4 *>(Tab + (((int64_t)v.w * a.ngroups + grp) * a.nkc + c) * (KC * RG));
+  };
+  auto load_a = [&](int it, floatx4 *r) {
+    const floatx4 *q = a_src(it);
+#pragma unroll
+    for (int i = 0; i < AR; ++i) {
+      const int e = threadIdx.x + 256 * i;
+      if (e < AV) r[i] = q[e];
     }
-  }
+  };
+  auto store_a = [&](int buf, const floatx4 *r) {
+    floatx4 *dst = reinterpret_cast<floatx4 *>(As[buf]);
+#pragma unroll
+    for (int i = 0; i < AR; ++i) {
+      const int e = threadIdx.x + 256 * i;
+      if (e < AV) dst[e] = r[i];
+    }
+  };
+
+  floatx16 acc[3];
+#pragma unroll
+  for (int t = 0; t < 3; ++t)
+#pragma unroll
+    for (int r = 0; r < 16; ++r) acc[t][r] = 0.f;
+
+  float b0[NS], b1[NS];
+  floatx4 ast[AR];
+  load_a(0, ast);
+  store_a(0, ast);
+  load_a(min(1, nit - 1), ast);
+  load_b(0, b0);
   __syncthreads();
-  for (int e = threadIdx.x; e < 64 * K; e += blockDim.x) {
-    const int j = e / K, row = e - j * K;
-    const int64_t P = (int64_t)chunk * 64 + j;
-    if (P < nparent) L[(off + 8 * P + cls) * K + row] = Acc[e];
+
+  // one (operator, chunk) iteration: stage the next operator, prefetch the
+  // next sources, then 3 x NS matrix-core steps on LDS buffer it & 1
+  auto body = [&](int it, const float *bc, float *bn) {
+    const int buf = it & 1;
+    store_a(buf ^ 1, ast);
+    load_a(min(it + 2, nit - 1), ast);
+    load_b(min(it + 1, nit - 1), bn);
+    const float *Ar = As[buf] + h * RG + j;
+#pragma unroll
+    for (int s2 = 0; s2 < NS; ++s2) {
+#pragma unroll
+      for (int t = 0; t < 3; ++t)
+        acc[t] = __builtin_amdgcn_mfma_f32_32x32x2f32(Ar[2 * s2 * RG + 32 * t], bc[s2], acc[t], 0, 0, 0);
+    }
+    __syncthreads();
+  };
+  for (int it = 0; it < nit; it += 2) {
+    body(it, b0, b1);
+    if (it + 1 < nit) body(it + 1, b1, b0);
+  }
+
+  // ---- results: lane (h, j) holds rows 8q + 4h + {0..3} of each row tile for target j
+  if (!valid) return;
+  const int64_t tb = off + 8 * P + cls;
+  float *dst = Out + ((int64_t)split * a.nbox + tb) * a.KS;
+#pragma unroll
+  for (int t = 0; t < 3; ++t)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int row = grp * RG + 32 * t + 8 * q + 4 * h;
+      if (row < a.KS) {
+        floatx4 v;
+        v[0] = acc[t][4 * q];
+        v[1] = acc[t][4 * q + 1];
+        v[2] = acc[t][4 * q + 2];
+        v[3] = acc[t][4 * q + 3];
+        *reinterpret_cast<floatx4 *>(dst + row) = v;
+      }
+    }
+}
+
+// L[b] = sum over operator ranges s (in order) of the partial locals, for the
+// boxes [b0, b1) of the M2L levels.
+__global__ void k_m2l_reduce(const floatx4 *__restrict__ part, floatx4 *__restrict__ L, int64_t v0, int64_t v1,
+                             int64_t stride, int nsplit) {
+  for (int64_t i = v0 + blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < v1; i += (int64_t)gridDim.x * blockDim.x) {
+    floatx4 s = part[i];
+    for (int k = 1; k < nsplit; ++k) s += part[i + k * stride];
+    L[i] = s;
   }
 }
 
 // Matrix-core tile check: C[rows x 64] = A[rows x kk] * B[kk x 64] with the same
-// fragment mapping as k_m2l (A given k-major as [kk][rows]).
+// fragment mapping as k_xlate (A given k-major as [kk][rows]).
 template <class T>
 __global__ void k_mfma_probe(const T *__restrict__ A, const T *__restrict__ B, T *__restrict__ C, int rows, int kk) {
   using MF = Mfma<T>;
@@ -904,7 +835,10 @@ __global__ void __launch_bounds__(256) k_p2p_l2p(const Atom4<T> *__restrict__ so
   }
   if (tid < BL) t_start[tid] = start[leafbase + tid];
   if (tid == 0) t_start[BL] = start[leafbase + BL];
-  for (int e = tid; e < BL * a.K; e += blockDim.x) loc[e] = Lleaf[(int64_t)leafbase * a.K + e];
+  for (int e = tid; e < BL * a.K; e += blockDim.x) {
+    const int i = e / a.K;
+    loc[e] = Lleaf[(int64_t)(leafbase + i) * a.KS + (e - i * a.K)];
+  }
   __syncthreads();
   if (tid == 0) {
     s_pre[0] = 0;
@@ -1285,34 +1219,14 @@ void launch_tree(const T *xyz, const T *qt, int64_t n, const Geom *g, int d, int
 }
 
 template <class T>
-void launch_p2m(const Atom4<T> *sorted, const int *start, int nleaf, int p, T *Mleaf, double *qds, const Geom *g, int d,
-                hipStream_t st) {
+void launch_p2m(const Atom4<T> *sorted, const int *start, int nleaf, int p, int KS, T *Mleaf, double *qds, const Geom *g,
+                int d, hipStream_t st) {
   const int K = (p + 1) * (p + 1);
   int chunk = (int)(16384 / (K * sizeof(T)));
   if (chunk > 64) chunk = 64;
   if (chunk < 1) chunk = 1;
-  hipLaunchKernelGGL(k_p2m<T>, dim3(nleaf), dim3(64), chunk * K * sizeof(T), st, sorted, start, p, K, chunk, Mleaf, qds,
+  hipLaunchKernelGGL(k_p2m<T>, dim3(nleaf), dim3(64), chunk * K * sizeof(T), st, sorted, start, p, K, KS, chunk, Mleaf, qds,
                      g, d);
-}
-
-static int pb_for(int K, size_t elem, int per_parent) {
-  int pb = (int)(32768 / (per_parent * K * elem));
-  return pb < 1 ? 1 : (pb > 8 ? 8 : pb);
-}
-
-template <class T>
-void launch_m2m(T *M, int lp, int K, const T *Tm, hipStream_t st) {
-  const int PB = pb_for(K, sizeof(T), 8);
-  const int64_t np = int64_t(1) << (3 * lp);
-  hipLaunchKernelGGL(k_m2m<T>, dim3((unsigned)((np + PB - 1) / PB)), dim3(128), PB * 8 * K * sizeof(T), st, M, lp, K,
-                     Tm, PB);
-}
-
-template <class T>
-void launch_l2l(T *L, int lc, int K, const T *Tl, hipStream_t st) {
-  const int PB = pb_for(K, sizeof(T), 1);
-  const int64_t np = int64_t(1) << (3 * (lc - 1));
-  hipLaunchKernelGGL(k_l2l<T>, dim3((unsigned)((np + PB - 1) / PB)), dim3(128), PB * K * sizeof(T), st, L, lc, K, Tl, PB);
 }
 
 template <class T>
@@ -1320,72 +1234,23 @@ void launch_lattice(const T *M, T *L, const double *LamT, int K, const double *q
   hipLaunchKernelGGL(k_lattice<T>, dim3(1), dim3(256), 0, st, M, L, LamT, K, qds, nleaf, g);
 }
 
-template <class T>
-void m2l_plan(int p, int d, int periodic, M2LArgs &a, int &blocks, int &threads, size_t &lds) {
-  using MF = Mfma<T>;
-  a.K = (p + 1) * (p + 1);
-  a.KK = (a.K + MF::TK - 1) / MF::TK * MF::TK;
-  a.nrt = (a.K + MF::TM - 1) / MF::TM;
-  a.RP = a.nrt * MF::TM;
-  a.ngroups = (a.nrt + 3) / 4;
-  a.nw = (a.nrt + a.ngroups - 1) / a.ngroups;
-  a.d = d;
-  a.periodic = periodic;
-  a.lmin = periodic ? 1 : 2;
-  const int budget = 40960;
-  int kc = budget / (kBStride * (int)sizeof(T));
-  kc = kc / MF::TK * MF::TK;
-  if (kc > a.KK) kc = a.KK;
-  a.kc = kc;
-  blocks = 0;
-  for (int l = 0; l <= 8; ++l) a.level_start[l] = 0;
-  for (int l = a.lmin; l <= d; ++l) {
-    a.level_start[l] = blocks;
-    const int64_t np = int64_t(1) << (3 * (l - 1));
-    blocks += (int)(8 * ((np + 63) / 64) * a.ngroups);
-  }
-  if (d + 1 <= 8) a.level_start[d + 1 <= 8 ? d + 1 : 8] = blocks;
-  threads = a.nw * 64;
-  lds = (size_t)a.kc * kBStride * sizeof(T);
-}
-
+// Operator tables: [slot][KK][RP], k padded with zero rows to whole chunks of
+// XChunk<T>::KC and rows padded to whole MFMA row tiles.
 template <class T>
 void m2l_table_layout(int p, int &KK, int &RP) {
   using MF = Mfma<T>;
+  constexpr int KC = XChunk<T>::KC;
   const int K = (p + 1) * (p + 1);
-  KK = (K + MF::TK - 1) / MF::TK * MF::TK;
+  KK = (K + KC - 1) / KC * KC;
   RP = (K + MF::TM - 1) / MF::TM * MF::TM;
-}
-
-template <class T>
-void launch_m2l(const T *M, T *L, const T *Tab, const int4 *lists, int p, int d, int periodic, hipStream_t st) {
-  M2LArgs a;
-  int blocks, threads;
-  size_t lds;
-  m2l_plan<T>(p, d, periodic, a, blocks, threads, lds);
-  if (blocks == 0) return;
-  hipLaunchKernelGGL(k_m2l<T>, dim3(blocks), dim3(threads), lds, st, M, L, Tab, lists, a);
-}
-
-template <class T>
-void launch_m2l_valu(const T *M, T *L, const T *Tab, const int4 *lists, int p, int d, int periodic, hipStream_t st) {
-  M2LArgs a;
-  int blocks, threads;
-  size_t lds;
-  m2l_plan<T>(p, d, periodic, a, blocks, threads, lds);
-  if (blocks == 0) return;
-  blocks /= a.ngroups;
-  for (int l = a.lmin; l <= d + 1 && l <= 8; ++l) a.level_start[l] /= a.ngroups;
-  hipLaunchKernelGGL(k_m2l_valu<T>, dim3(blocks), dim3(256), (size_t)2 * 64 * a.K * sizeof(T), st, M, L, Tab, lists, a);
 }
 
 template <class T>
 void xlate_geometry(int p, XArgs &a) {
   using MF = Mfma<T>;
   a.K = (p + 1) * (p + 1);
-  a.KK = (a.K + MF::TK - 1) / MF::TK * MF::TK;
-  a.nrt = (a.K + MF::TM - 1) / MF::TM;
-  a.RP = a.nrt * MF::TM;
+  m2l_table_layout<T>(p, a.KK, a.RP);
+  a.nrt = a.RP / MF::TM;
   a.ngroups = (a.nrt + 3) / 4;
   a.nw = (a.nrt + a.ngroups - 1) / a.ngroups;
 }
@@ -1395,10 +1260,24 @@ static size_t xlate_lds() {
   return (size_t)2 * XChunk<T>::KC * kBStride * sizeof(T);
 }
 
+// One wave per output row tile of a group, at least 3 waves (the gather
+// uses 3 or 4 threads per target).  Blocks of exactly the active waves keep
+// every SIMD of a CU busy with matrix-core work.
+template <class T, int MODE, class... Args>
+static void xlate_launch(const XArgs &a, int blocks, hipStream_t st, Args... args) {
+  if (a.nw <= 3)
+    hipLaunchKernelGGL((k_xlate<T, MODE, 3>), dim3(blocks), dim3(192), xlate_lds<T>(), st, args..., a);
+  else
+    hipLaunchKernelGGL((k_xlate<T, MODE, 4>), dim3(blocks), dim3(256), xlate_lds<T>(), st, args..., a);
+}
+
+
 template <class T>
-void launch_xlate_m2l(const T *M, T *L, const T *Tab, const int4 *lists, int p, int d, int periodic, hipStream_t st) {
+void launch_xlate_m2l(const T *M, T *L, const T *Tab, const int4 *lists, int p, int KS, int d, int periodic,
+                      hipStream_t st) {
   XArgs a;
   xlate_geometry<T>(p, a);
+  a.KS = KS;
   a.d = d;
   a.periodic = periodic;
   a.lmin = periodic ? 1 : 2;
@@ -1413,13 +1292,14 @@ void launch_xlate_m2l(const T *M, T *L, const T *Tab, const int4 *lists, int p, 
   }
   if (d + 1 <= 8) a.level_start[d + 1] = blocks;
   if (blocks == 0) return;
-  hipLaunchKernelGGL((k_xlate<T, XL_M2L>), dim3(blocks), dim3(256), xlate_lds<T>(), st, M, L, Tab, lists, a);
+  xlate_launch<T, XL_M2L>(a, blocks, st, M, L, Tab, lists);
 }
 
 template <class T>
-void launch_xlate_m2m(T *M, int lp, const T *Tab, const int4 *ops, int p, hipStream_t st) {
+void launch_xlate_m2m(T *M, int lp, const T *Tab, const int4 *ops, int p, int KS, hipStream_t st) {
   XArgs a;
   xlate_geometry<T>(p, a);
+  a.KS = KS;
   a.d = lp + 1;
   a.periodic = 0;
   a.lmin = 0;
@@ -1427,13 +1307,14 @@ void launch_xlate_m2m(T *M, int lp, const T *Tab, const int4 *ops, int p, hipStr
   a.level = lp;
   const int64_t np = int64_t(1) << (3 * lp);
   const int blocks = (int)(((np + 63) / 64) * a.ngroups);
-  hipLaunchKernelGGL((k_xlate<T, XL_M2M>), dim3(blocks), dim3(256), xlate_lds<T>(), st, M, M, Tab, ops, a);
+  xlate_launch<T, XL_M2M>(a, blocks, st, (const T *)M, M, Tab, ops);
 }
 
 template <class T>
-void launch_xlate_l2l(T *L, int lc, const T *Tab, const int4 *ops, int p, hipStream_t st) {
+void launch_xlate_l2l(T *L, int lc, const T *Tab, const int4 *ops, int p, int KS, hipStream_t st) {
   XArgs a;
   xlate_geometry<T>(p, a);
+  a.KS = KS;
   a.d = lc;
   a.periodic = 0;
   a.lmin = 0;
@@ -1441,7 +1322,81 @@ void launch_xlate_l2l(T *L, int lc, const T *Tab, const int4 *ops, int p, hipStr
   a.level = lc;
   const int64_t np = int64_t(1) << (3 * (lc - 1));
   const int blocks = (int)(8 * ((np + 63) / 64) * a.ngroups);
-  hipLaunchKernelGGL((k_xlate<T, XL_L2L>), dim3(blocks), dim3(256), xlate_lds<T>(), st, L, L, Tab, ops, a);
+  xlate_launch<T, XL_L2L>(a, blocks, st, (const T *)L, L, Tab, ops);
+}
+
+// ---- float32 M2L plan: tiles of 128 targets, row groups of 96, operator ranges
+void m2l32_plan(int p, int d, int periodic, int n_cu, M2LPlan &a) {
+  a.K = (p + 1) * (p + 1);
+  a.nkc = (a.K + kM2LKC - 1) / kM2LKC;
+  a.KS = a.nkc * kM2LKC;
+  a.ngroups = (a.K + kM2LRowGroup - 1) / kM2LRowGroup;
+  a.d = d;
+  a.periodic = periodic;
+  a.lmin = periodic ? 1 : 2;
+  a.nbox = level_offset(d + 1);
+  a.zbox = a.nbox;
+  a.ntiles = 0;
+  for (int l = 0; l <= 8; ++l) a.tiles_start[l] = 0;
+  for (int l = a.lmin; l <= d; ++l) {
+    a.tiles_start[l] = a.ntiles;
+    const int64_t ntg = int64_t(1) << (3 * (l - 1));
+    a.ntiles += (int)(8 * ((ntg + kM2LTile - 1) / kM2LTile));
+  }
+  if (d + 1 <= 8) a.tiles_start[d + 1] = a.ntiles;
+  // operator ranges: choose the split count that minimises the modelled
+  // makespan with two resident blocks per CU (one item costs its operator
+  // count plus a fixed overhead; every extra partial costs a read and write)
+  a.nsplit = 1;
+  if (a.ntiles > 0) {
+    const double slots = 2.0 * (n_cu > 0 ? n_cu : 256);
+    double best = 1e300;
+    for (int s = 1; s <= kM2LMaxSplit; ++s) {
+      const double items = (double)a.ntiles * a.ngroups * s;
+      const double rounds = std::ceil(items / slots);
+      const double cost = rounds * (std::ceil((double)kListLen / s) * a.nkc + 2.0) + 0.5 * (s > 1 ? s : 0);
+      if (cost < best - 1e-9) {
+        best = cost;
+        a.nsplit = s;
+      }
+    }
+  }
+}
+
+void launch_m2l_f32(const float *M, float *L, float *part, const float *Tab, const int4 *lists, const M2LPlan &a,
+                    hipStream_t st) {
+  if (a.ntiles == 0) return;
+  const int blocks = a.nsplit * a.ngroups * a.ntiles;
+  float *out = a.nsplit > 1 ? part : L;
+  hipLaunchKernelGGL(k_m2l_f32<kM2LKC>, dim3(blocks), dim3(256), 0, st, M, out, Tab, lists, a);
+  if (a.nsplit > 1) {
+    const int64_t b0 = level_offset(a.lmin), b1 = level_offset(a.d + 1);
+    const int64_t v0 = b0 * a.KS / 4, v1 = b1 * a.KS / 4;
+    const int64_t n = v1 - v0;
+    const int grid = (int)std::min<int64_t>((n + 255) / 256, 4096);
+    hipLaunchKernelGGL(k_m2l_reduce, dim3(grid), dim3(256), 0, st, reinterpret_cast<const floatx4 *>(part),
+                       reinterpret_cast<floatx4 *>(L), v0, v1, a.nbox * a.KS / 4, a.nsplit);
+  }
+}
+
+// Host layout of the float32 M2L operator table: [slot][row group][chunk][r][96]
+// where LDS row r = 2s + h of a chunk holds k = 4(r/4) + 2(r%2) + (r/2)%2.
+void m2l32_table(const M2LPlan &a, int slot, const double *Tv, float *dst) {
+  const int K = a.K;
+  for (int g = 0; g < a.ngroups; ++g)
+    for (int c = 0; c < a.nkc; ++c)
+      for (int r = 0; r < kM2LKC; ++r) {
+        const int k = c * kM2LKC + 4 * (r >> 2) + 2 * (r & 1) + ((r >> 1) & 1);
+        float *row = dst + ((((size_t)slot * a.ngroups + g) * a.nkc + c) * kM2LKC + r) * kM2LRowGroup;
+        for (int i = 0; i < kM2LRowGroup; ++i) {
+          const int orow = g * kM2LRowGroup + i;
+          row[i] = (orow < K && k < K) ? (float)Tv[(size_t)orow * K + k] : 0.f;
+        }
+      }
+}
+
+size_t m2l32_table_size(const M2LPlan &a, int nslots) {
+  return (size_t)nslots * a.ngroups * a.nkc * kM2LKC * kM2LRowGroup;
 }
 
 template <class T>
@@ -1456,9 +1411,10 @@ int p2p_blocks(int d) {
 }
 
 template <class T>
-void launch_p2p(const Atom4<T> *sorted, const int *start, const int *perm, const T *Lleaf, const Geom *g, int d,
+void launch_p2p(const Atom4<T> *sorted, const int *start, const int *perm, const T *Lleaf, int KS, const Geom *g, int d,
                 int periodic, int p, double ke, T *phi_sorted, T *F, T *pot_user, double *epart, hipStream_t st) {
   P2PArgs a;
+  a.KS = KS;
   a.d = d;
   a.periodic = periodic;
   a.p = p;
@@ -1499,19 +1455,16 @@ void launch_finalize(const double *epart, int nb, const double *dE_site, int ns,
 #define MAHI_INST(T)                                                                                                 \
   template void launch_bbox<T>(const T *, int64_t, double *, int, Geom *, hipStream_t);                             \
   template void launch_tree<T>(const T *, const T *, int64_t, const Geom *, int, int, TreeBufs<T>, hipStream_t);     \
-  template void launch_p2m<T>(const Atom4<T> *, const int *, int, int, T *, double *, const Geom *, int, hipStream_t); \
-  template void launch_m2m<T>(T *, int, int, const T *, hipStream_t);                                               \
-  template void launch_l2l<T>(T *, int, int, const T *, hipStream_t);                                               \
+  template void launch_p2m<T>(const Atom4<T> *, const int *, int, int, int, T *, double *, const Geom *, int,         \
+                              hipStream_t);                                                                         \
   template void launch_lattice<T>(const T *, T *, const double *, int, const double *, int, Geom *, hipStream_t);    \
-  template void launch_m2l<T>(const T *, T *, const T *, const int4 *, int, int, int, hipStream_t);                 \
   template void m2l_table_layout<T>(int, int &, int &);                                                               \
   template void launch_mfma_probe<T>(const T *, const T *, T *, int, int, hipStream_t);                              \
-  template void launch_m2l_valu<T>(const T *, T *, const T *, const int4 *, int, int, int, hipStream_t);       \
-  template void launch_xlate_m2l<T>(const T *, T *, const T *, const int4 *, int, int, int, hipStream_t);      \
-  template void launch_xlate_m2m<T>(T *, int, const T *, const int4 *, int, hipStream_t);                      \
-  template void launch_xlate_l2l<T>(T *, int, const T *, const int4 *, int, hipStream_t);                              \
+  template void launch_xlate_m2l<T>(const T *, T *, const T *, const int4 *, int, int, int, int, hipStream_t);         \
+  template void launch_xlate_m2m<T>(T *, int, const T *, const int4 *, int, int, hipStream_t);                        \
+  template void launch_xlate_l2l<T>(T *, int, const T *, const int4 *, int, int, hipStream_t);                        \
   template int p2p_blocks<T>(int);                                                                                   \
-  template void launch_p2p<T>(const Atom4<T> *, const int *, const int *, const T *, const Geom *, int, int, int,    \
+  template void launch_p2p<T>(const Atom4<T> *, const int *, const int *, const T *, int, const Geom *, int, int, int, \
                               double, T *, T *, T *, double *, hipStream_t);                                         \
   template void launch_charge_scale<T>(const SiteArgs &, const double *, T *, hipStream_t);                          \
   template void launch_site<T>(const SiteArgs &, const T *, const int *, const T *, const Geom *, const double *,    \

@@ -6,20 +6,27 @@
 
 namespace mahi {
 
-struct M2LArgs {
-  int K, KK, RP, nrt, nw, ngroups, kc;
+// float32 M2L: 128 targets per block, 96-row groups, k chunks of 84
+constexpr int kM2LKC = 84;
+constexpr int kM2LTile = 128;
+constexpr int kM2LRowGroup = 96;
+constexpr int kM2LMaxSplit = 8;
+
+struct M2LPlan {
+  int K, KS, nkc, ngroups, nsplit, ntiles;
   int d, lmin, periodic;
-  int level_start[9];
+  int64_t nbox, zbox;  // boxes over all levels; index of the all-zero multipole row
+  int tiles_start[9];
 };
 
 struct XArgs {
-  int K, KK, RP, nrt, nw, ngroups;
+  int K, KS, KK, RP, nrt, nw, ngroups;
   int d, lmin, periodic, nops, level;
   int level_start[9];
 };
 
 struct P2PArgs {
-  int d, periodic, p, K, cap;
+  int d, periodic, p, K, KS, cap;
   double ke;
 };
 
@@ -46,25 +53,25 @@ template <class T> void launch_bbox(const T *xyz, int64_t n, double *part, int n
 template <class T>
 void launch_tree(const T *xyz, const T *qt, int64_t n, const Geom *g, int d, int periodic, TreeBufs<T> b, hipStream_t st);
 template <class T>
-void launch_p2m(const Atom4<T> *sorted, const int *start, int nleaf, int p, T *Mleaf, double *qds, const Geom *g, int d,
-                hipStream_t st);
-template <class T> void launch_m2m(T *M, int lp, int K, const T *Tm, hipStream_t st);
-template <class T> void launch_l2l(T *L, int lc, int K, const T *Tl, hipStream_t st);
+void launch_p2m(const Atom4<T> *sorted, const int *start, int nleaf, int p, int KS, T *Mleaf, double *qds, const Geom *g,
+                int d, hipStream_t st);
 template <class T>
 void launch_lattice(const T *M, T *L, const double *LamT, int K, const double *qds, int nleaf, Geom *g, hipStream_t st);
 template <class T> void m2l_table_layout(int p, int &KK, int &RP);
 template <class T>
-void launch_m2l(const T *M, T *L, const T *Tab, const int4 *lists, int p, int d, int periodic, hipStream_t st);
-template <class T>
-void launch_m2l_valu(const T *M, T *L, const T *Tab, const int4 *lists, int p, int d, int periodic, hipStream_t st);
-template <class T>
-void launch_xlate_m2l(const T *M, T *L, const T *Tab, const int4 *lists, int p, int d, int periodic, hipStream_t st);
-template <class T> void launch_xlate_m2m(T *M, int lp, const T *Tab, const int4 *ops, int p, hipStream_t st);
-template <class T> void launch_xlate_l2l(T *L, int lc, const T *Tab, const int4 *ops, int p, hipStream_t st);
+void launch_xlate_m2l(const T *M, T *L, const T *Tab, const int4 *lists, int p, int KS, int d, int periodic,
+                      hipStream_t st);
+template <class T> void launch_xlate_m2m(T *M, int lp, const T *Tab, const int4 *ops, int p, int KS, hipStream_t st);
+template <class T> void launch_xlate_l2l(T *L, int lc, const T *Tab, const int4 *ops, int p, int KS, hipStream_t st);
+void m2l32_plan(int p, int d, int periodic, int n_cu, M2LPlan &a);
+void launch_m2l_f32(const float *M, float *L, float *part, const float *Tab, const int4 *lists, const M2LPlan &a,
+                    hipStream_t st);
+void m2l32_table(const M2LPlan &a, int slot, const double *Tv, float *dst);
+size_t m2l32_table_size(const M2LPlan &a, int nslots);
 template <class T> void launch_mfma_probe(const T *A, const T *B, T *C, int rows, int kk, hipStream_t st);
 template <class T> int p2p_blocks(int d);
 template <class T>
-void launch_p2p(const Atom4<T> *sorted, const int *start, const int *perm, const T *Lleaf, const Geom *g, int d,
+void launch_p2p(const Atom4<T> *sorted, const int *start, const int *perm, const T *Lleaf, int KS, const Geom *g, int d,
                 int periodic, int p, double ke, T *phi_sorted, T *F, T *pot_user, double *epart, hipStream_t st);
 template <class T> void launch_charge_scale(const SiteArgs &s, const double *lam, T *qt, hipStream_t st);
 template <class T>
