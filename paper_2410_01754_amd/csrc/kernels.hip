@@ -597,24 +597,28 @@ __global__ void __launch_bounds__(64 * TPT) k_xlate(const T *X, T *Y, const T *_
 // tiles of the group.  For every (operator v, k chunk):
 //   * the block stages T_v (96 rows x KC) once in LDS (double buffered);
 //   * each wave holds its 32 gathered source multipoles in registers, loaded
-//     as float2 from the padded multipole rows (stride KS, a multiple of 4);
-//   * each wave runs 3 x KC/2 MFMA 32x32x2 into 3 accumulator tiles.
-// In k-step s the lanes of half h (lane >> 5) contract k = 4(s/2) + 2h + s%2:
-// the k index of one MFMA is internal to the instruction, so any pairing of
-// the two halves works as long as A and B agree.  The operator rows are
-// stored pre-permuted (LDS row 2s + h holds that k), and each lane's B values
-// are pairs of consecutive k.  Several operator ranges of one target tile
-// write separate partial sums that k_m2l_reduce adds in a fixed order.
+//     as float4 from the padded multipole rows (stride KS, a multiple of 8);
+//   * each wave runs 3 x NS MFMA 32x32x2 into 3 accumulator tiles.
+// In k-step s the lanes of half h (lane >> 5) contract
+//   k = 8 (s / 4) + 4 h + s % 4
+// (the k index of one MFMA is internal to the instruction, so any pairing of
+// the two halves works as long as A and B agree): each lane's B values are
+// runs of 4 consecutive k, one float4 load per 4 steps.  The operator rows are
+// stored pre-permuted (LDS row 2s + h holds that k).  A chunk of NS = 40 steps
+// covers 80 consecutive k; the single chunk of NS = 42 steps used for
+// (p+1)^2 = 81 covers k <= 81 (it skips 82, 83, which do not exist there).
+// Several operator ranges of one target tile write separate partial sums that
+// k_m2l_reduce adds in a fixed order.
 // ---------------------------------------------------------------------------
 typedef float floatx4 __attribute__((ext_vector_type(4)));
 
-template <int KC>
+template <int NS>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2)))
 k_m2l_f32(const float *__restrict__ M, float *__restrict__ Out, const float *__restrict__ Tab,
           const int4 *__restrict__ lists, M2LPlan a) {
   constexpr int RG = kM2LRowGroup;  // rows per group (3 tiles of 32)
-  constexpr int NS = KC / 2;        // MFMA k-steps per chunk
-  constexpr int NQ = KC / 4;        // float2 loads per lane per chunk
+  constexpr int KC = 2 * NS;        // operator rows (k values) per chunk
+  constexpr int NQ = (NS + 3) / 4;  // float4 loads per lane per chunk
   constexpr int AV = KC * RG / 4;   // float4 elements of one staged operator chunk
   constexpr int AR = (AV + 255) / 256;
   __shared__ float As[2][KC * RG];
@@ -661,12 +665,13 @@ k_m2l_f32(const float *__restrict__ M, float *__restrict__ Out, const float *__r
   };
   auto load_b = [&](int it, float *b) {
     const int c = it % a.nkc;
-    const float2 *q = reinterpret_cast<const float2 *>(M + src_row(it) * a.KS + c * KC + 2 * h);
+    const floatx4 *q = reinterpret_cast<const floatx4 *>(M + src_row(it) * a.KS + c * kM2LKC + 4 * h);
 #pragma unroll
     for (int i = 0; i < NQ; ++i) {
-      const float2 v = q[2 * i];
-      b[2 * i] = v.x;
-      b[2 * i + 1] = v.y;
+      const floatx4 v = q[2 * i];
+#pragma unroll
+      for (int e = 0; e < 4; ++e)
+        if (4 * i + e < NS) b[4 * i + e] = v[e];
     }
   };
   auto a_src = [&](int it) {
@@ -1328,8 +1333,16 @@ void launch_xlate_l2l(T *L, int lc, const T *Tab, const int4 *ops, int p, int KS
 // ---- float32 M2L plan: tiles of 128 targets, row groups of 96, operator ranges
 void m2l32_plan(int p, int d, int periodic, int n_cu, M2LPlan &a) {
   a.K = (p + 1) * (p + 1);
-  a.nkc = (a.K + kM2LKC - 1) / kM2LKC;
-  a.KS = a.nkc * kM2LKC;
+  if (a.K > kM2LKC && a.K <= 82) {
+    // one chunk of 42 steps (k <= 81; rows read up to k = 87)
+    a.ns = 42;
+    a.nkc = 1;
+    a.KS = 88;
+  } else {
+    a.ns = 40;
+    a.nkc = (a.K + kM2LKC - 1) / kM2LKC;
+    a.KS = a.nkc * kM2LKC;
+  }
   a.ngroups = (a.K + kM2LRowGroup - 1) / kM2LRowGroup;
   a.d = d;
   a.periodic = periodic;
@@ -1368,7 +1381,10 @@ void launch_m2l_f32(const float *M, float *L, float *part, const float *Tab, con
   if (a.ntiles == 0) return;
   const int blocks = a.nsplit * a.ngroups * a.ntiles;
   float *out = a.nsplit > 1 ? part : L;
-  hipLaunchKernelGGL(k_m2l_f32<kM2LKC>, dim3(blocks), dim3(256), 0, st, M, out, Tab, lists, a);
+  if (a.ns == 42)
+    hipLaunchKernelGGL(k_m2l_f32<42>, dim3(blocks), dim3(256), 0, st, M, out, Tab, lists, a);
+  else
+    hipLaunchKernelGGL(k_m2l_f32<40>, dim3(blocks), dim3(256), 0, st, M, out, Tab, lists, a);
   if (a.nsplit > 1) {
     const int64_t b0 = level_offset(a.lmin), b1 = level_offset(a.d + 1);
     const int64_t v0 = b0 * a.KS / 4, v1 = b1 * a.KS / 4;
@@ -1380,14 +1396,15 @@ void launch_m2l_f32(const float *M, float *L, float *part, const float *Tab, con
 }
 
 // Host layout of the float32 M2L operator table: [slot][row group][chunk][r][96]
-// where LDS row r = 2s + h of a chunk holds k = 4(r/4) + 2(r%2) + (r/2)%2.
+// where LDS row r = 2s + h of a chunk holds k = 8(s/4) + 4h + s%4.
 void m2l32_table(const M2LPlan &a, int slot, const double *Tv, float *dst) {
-  const int K = a.K;
+  const int K = a.K, KC = 2 * a.ns;
   for (int g = 0; g < a.ngroups; ++g)
     for (int c = 0; c < a.nkc; ++c)
-      for (int r = 0; r < kM2LKC; ++r) {
-        const int k = c * kM2LKC + 4 * (r >> 2) + 2 * (r & 1) + ((r >> 1) & 1);
-        float *row = dst + ((((size_t)slot * a.ngroups + g) * a.nkc + c) * kM2LKC + r) * kM2LRowGroup;
+      for (int r = 0; r < KC; ++r) {
+        const int s = r >> 1, h = r & 1;
+        const int k = c * kM2LKC + 8 * (s >> 2) + 4 * h + (s & 3);
+        float *row = dst + ((((size_t)slot * a.ngroups + g) * a.nkc + c) * KC + r) * kM2LRowGroup;
         for (int i = 0; i < kM2LRowGroup; ++i) {
           const int orow = g * kM2LRowGroup + i;
           row[i] = (orow < K && k < K) ? (float)Tv[(size_t)orow * K + k] : 0.f;
@@ -1396,7 +1413,7 @@ void m2l32_table(const M2LPlan &a, int slot, const double *Tv, float *dst) {
 }
 
 size_t m2l32_table_size(const M2LPlan &a, int nslots) {
-  return (size_t)nslots * a.ngroups * a.nkc * kM2LKC * kM2LRowGroup;
+  return (size_t)nslots * a.ngroups * a.nkc * (2 * a.ns) * kM2LRowGroup;
 }
 
 template <class T>

@@ -6,14 +6,15 @@
 
 namespace mahi {
 
-// float32 M2L: 128 targets per block, 96-row groups, k chunks of 84
-constexpr int kM2LKC = 84;
+// float32 M2L: 128 targets per block, 96-row groups, k chunks of 80
+// (a single 42-step chunk when (p+1)^2 = 81)
+constexpr int kM2LKC = 80;
 constexpr int kM2LTile = 128;
 constexpr int kM2LRowGroup = 96;
 constexpr int kM2LMaxSplit = 8;
 
 struct M2LPlan {
-  int K, KS, nkc, ngroups, nsplit, ntiles;
+  int K, KS, ns, nkc, ngroups, nsplit, ntiles;
   int d, lmin, periodic;
   int64_t nbox, zbox;  // boxes over all levels; index of the all-zero multipole row
   int tiles_start[9];
