@@ -789,38 +789,162 @@ __global__ void k_mfma_probe(const T *__restrict__ A, const T *__restrict__ B, T
 
 // ---------------------------------------------------------------------------
 // Near field + far-field evaluation at the atoms + outputs.
-// A block owns the 2x2x2 leaves of one level d-1 box (the single leaf when
-// d = 0).  It stages the atoms of the surrounding 4x4x4 leaves (3x3x3 images
-// at d = 0) in LDS, in block-centred leaf units with each neighbour's periodic
-// image shift already applied, in chunks of at most `cap` atoms.  Each thread
-// owns one target atom: it sums q/r and q r/r^3 over its 27 neighbour leaves,
-// then evaluates its leaf's local expansion (potential and gradient), adds the
-// r^2 part of the lattice remainder, and writes the potential (sorted order),
-// the force (user order) and the block's float64 energy partial.
+// One 64-lane block per leaf (blocks of one XCD take one contiguous Morton
+// range, i.e. one spatial octant, so neighbour atoms stay in that XCD's L2).
+// The sources are read straight from the sorted atoms, neighbour leaf by
+// neighbour leaf (leaf-local coordinates; the neighbour's offset, which also
+// carries the periodic image shift, is applied to the targets once per
+// neighbour).  A pass covers up to 64 targets of the leaf: each lane owns M
+// targets (p, p + P, ...) and one of G source groups (every G-th source), with
+// M chosen for the best lane utilisation; the G group partials are summed in
+// group order with cross-lane reads.  Only the leaf itself can hold the
+// target atom, so only that neighbour skips r = 0.  Then one lane per target
+// evaluates the leaf's local expansion (potential and gradient; the gradient's
+// coefficients are formed once per leaf), adds the r^2 part of the lattice
+// remainder, and writes the potential (sorted order), the force (user order)
+// and its share of the leaf's float64 energy.
 // ---------------------------------------------------------------------------
+struct P2PPass {
+  int P, G;  // targets per group row, source groups
+};
+
+__device__ __forceinline__ P2PPass p2p_pass_shape(int nt, int &M) {
+  // maximise nt * G / (64 M) over M = 1, 2, 3 with P = ceil(nt / M), G = 64 / P
+  int bestM = 1, bestG = 64 / max(nt, 1);
+  float best = (float)nt * bestG / 64.f;
+  for (int m = 2; m <= 3; ++m) {
+    const int P = (nt + m - 1) / m;
+    const int G = 64 / max(P, 1);
+    const float u = (float)nt * G / (64.f * m);
+    if (u > best + 1e-6f) {
+      best = u;
+      bestM = m;
+    }
+  }
+  M = bestM;
+  const int P = (nt + M - 1) / M;
+  return {max(P, 1), 64 / max(P, 1)};
+}
+
+template <class T, int M, bool SELF>
+__device__ __forceinline__ void p2p_pair(const Atom4<T> &o, const T (&px)[M], const T (&py)[M], const T (&pz)[M],
+                                         T (&phi)[M], T (&ex)[M], T (&ey)[M], T (&ez)[M]) {
+#pragma unroll
+  for (int m = 0; m < M; ++m) {
+    const T rx = px[m] - o.x, ry = py[m] - o.y, rz = pz[m] - o.z;
+    const T r2 = rx * rx + ry * ry + rz * rz;
+    T ri = rsqrt_t<T>(r2);
+    if (SELF) ri = r2 > T(0) ? ri : T(0);
+    const T qr = o.q * ri;
+    phi[m] += qr;
+    const T f = qr * ri * ri;
+    ex[m] += f * rx;
+    ey[m] += f * ry;
+    ez[m] += f * rz;
+  }
+}
+
+// Sources s[g], s[g + G], ... of one neighbour leaf (cnt atoms), with the next
+// two loaded before the current two are used.
+template <class T, int M, bool SELF>
+__device__ __forceinline__ void p2p_run(const Atom4<T> *__restrict__ s, int cnt, int g, int G, const T (&px)[M],
+                                        const T (&py)[M], const T (&pz)[M], T (&phi)[M], T (&ex)[M], T (&ey)[M],
+                                        T (&ez)[M]) {
+  int j = g;
+  if (j >= cnt) return;
+  const int last = cnt - 1;
+  Atom4<T> o0 = s[j], o1 = s[min(j + G, last)];
+  for (; j + G < cnt; j += 2 * G) {
+    const Atom4<T> n0 = s[min(j + 2 * G, last)], n1 = s[min(j + 3 * G, last)];
+    p2p_pair<T, M, SELF>(o0, px, py, pz, phi, ex, ey, ez);
+    p2p_pair<T, M, SELF>(o1, px, py, pz, phi, ex, ey, ez);
+    o0 = n0;
+    o1 = n1;
+  }
+  if (j < cnt) p2p_pair<T, M, SELF>(o0, px, py, pz, phi, ex, ey, ez);
+}
+
 template <class T>
-__global__ void __launch_bounds__(256) k_p2p_l2p(const Atom4<T> *__restrict__ sorted, const int *__restrict__ start,
-                                                 const int *__restrict__ perm, const T *__restrict__ Lleaf,
-                                                 const Geom *__restrict__ gp, P2PArgs a, T *__restrict__ phi_sorted,
-                                                 T *__restrict__ F, T *__restrict__ pot_user,
-                                                 double *__restrict__ epart) {
+__device__ __forceinline__ T shfl_t(T v, int src) {
+  return __shfl(v, src, 64);
+}
+
+// One pass: targets [tp, tp + nt) (nt <= 64) against the 27 neighbour leaves
+// (start and count per neighbour in nb_st / nb_ct).  Lane u < nt receives the
+// sums for target u (leaf units) in acc.
+template <class T, int M>
+__device__ __forceinline__ void p2p_wave(const Atom4<T> *__restrict__ sorted, const int *nb_st, const int *nb_ct,
+                                         int tp, int nt, int lane, P2PPass ps, T (&acc)[4]) {
+  const int p = lane % ps.P, g = lane / ps.P;
+  T qx[M], qy[M], qz[M], phi[M], ex[M], ey[M], ez[M];
+#pragma unroll
+  for (int m = 0; m < M; ++m) {
+    const int u = p + m * ps.P;
+    Atom4<T> me = {T(0), T(0), T(0), T(0)};
+    if (u < nt) me = sorted[tp + u];
+    qx[m] = me.x;
+    qy[m] = me.y;
+    qz[m] = me.z;
+    phi[m] = ex[m] = ey[m] = ez[m] = T(0);
+  }
+  if (g < ps.G) {
+    for (int r = 0; r < 27; ++r) {
+      const int cnt = nb_ct[r];
+      if (cnt == 0) continue;
+      // target relative to the neighbour's centre: subtract the neighbour offset
+      const T sx = (T)(r / 9 - 1), sy = (T)((r / 3) % 3 - 1), sz = (T)(r % 3 - 1);
+      T px[M], py[M], pz[M];
+#pragma unroll
+      for (int m = 0; m < M; ++m) {
+        px[m] = qx[m] - sx;
+        py[m] = qy[m] - sy;
+        pz[m] = qz[m] - sz;
+      }
+      if (r == 13) p2p_run<T, M, true>(sorted + nb_st[r], cnt, g, ps.G, px, py, pz, phi, ex, ey, ez);
+      else p2p_run<T, M, false>(sorted + nb_st[r], cnt, g, ps.G, px, py, pz, phi, ex, ey, ez);
+    }
+  }
+  // lane u (target u = p' + m' P) gathers its sums from lanes g P + p' in group order
+  const int pu = lane % ps.P, mu = lane / ps.P;
+#pragma unroll
+  for (int m = 0; m < M; ++m) {
+    T s0 = T(0), s1 = T(0), s2 = T(0), s3 = T(0);
+    for (int gg = 0; gg < ps.G; ++gg) {
+      const int sl = gg * ps.P + pu;
+      s0 += shfl_t(phi[m], sl);
+      s1 += shfl_t(ex[m], sl);
+      s2 += shfl_t(ey[m], sl);
+      s3 += shfl_t(ez[m], sl);
+    }
+    if (mu == m) {
+      acc[0] += s0;
+      acc[1] += s1;
+      acc[2] += s2;
+      acc[3] += s3;
+    }
+  }
+}
+
+template <class T>
+__global__ void __launch_bounds__(64) k_p2p_l2p(const Atom4<T> *__restrict__ sorted, const int *__restrict__ start,
+                                                const int *__restrict__ perm, const T *__restrict__ Lleaf,
+                                                const Geom *__restrict__ gp, P2PArgs a, T *__restrict__ phi_sorted,
+                                                T *__restrict__ F, T *__restrict__ pot_user,
+                                                double *__restrict__ epart) {
   extern __shared__ unsigned char smem_raw[];
-  Atom4<T> *src = reinterpret_cast<Atom4<T> *>(smem_raw);
-  T *loc = reinterpret_cast<T *>(src + a.cap);  // [BL][K] leaf local expansions
-  __shared__ int s_start[64], s_pre[65], t_start[9];
-  __shared__ double s_red[4];
+  T *loc = reinterpret_cast<T *>(smem_raw);  // [KL]: L, then (dloc) Dx, Dy, Dz
+  __shared__ int nb_st[27], nb_ct[27];
 
-  const int tid = threadIdx.x;
+  const int lane = threadIdx.x;
   const int n = 1 << a.d;
-  const int BW = n >= 2 ? 2 : 1, SW = BW + 2, BL = BW * BW * BW, NS = SW * SW * SW;
+  const int nleaf = n * n * n;
+  const int bid = blockIdx.x;
+  const int leaf = nleaf >= 8 ? (bid & 7) * (nleaf >> 3) + (bid >> 3) : bid;
   int bx = 0, by = 0, bz = 0;
-  if (a.d >= 1) unmorton(blockIdx.x, bx, by, bz);
-  const int b0x = bx * BW, b0y = by * BW, b0z = bz * BW;
-  const int leafbase = a.d >= 1 ? (int)blockIdx.x * 8 : 0;
+  unmorton((uint32_t)leaf, bx, by, bz);
 
-  if (tid < NS) {
-    const int sx = tid / (SW * SW), sy = (tid / SW) % SW, sz = tid % SW;
-    int cx = b0x - 1 + sx, cy = b0y - 1 + sy, cz = b0z - 1 + sz;
+  if (lane < 27) {
+    int cx = bx - 1 + lane / 9, cy = by - 1 + (lane / 3) % 3, cz = bz - 1 + lane % 3;
     bool ok = true;
     if (a.periodic) {
       cx = (cx + n) % n;
@@ -831,113 +955,92 @@ __global__ void __launch_bounds__(256) k_p2p_l2p(const Atom4<T> *__restrict__ so
     }
     int st = 0, cnt = 0;
     if (ok) {
-      const int leaf = (int)morton(cx, cy, cz);
-      st = start[leaf];
-      cnt = start[leaf + 1] - st;
+      const int nb = (int)morton(cx, cy, cz);
+      st = start[nb];
+      cnt = start[nb + 1] - st;
     }
-    s_start[tid] = st;
-    s_pre[tid + 1] = cnt;  // prefix formed below
+    nb_st[lane] = st;
+    nb_ct[lane] = cnt;
   }
-  if (tid < BL) t_start[tid] = start[leafbase + tid];
-  if (tid == 0) t_start[BL] = start[leafbase + BL];
-  for (int e = tid; e < BL * a.K; e += blockDim.x) {
-    const int i = e / a.K;
-    loc[e] = Lleaf[(int64_t)(leafbase + i) * a.KS + (e - i * a.K)];
-  }
+  for (int e = lane; e < a.K; e += 64) loc[e] = Lleaf[(int64_t)leaf * a.KS + e];
   __syncthreads();
-  if (tid == 0) {
-    s_pre[0] = 0;
-    for (int s = 0; s < NS; ++s) s_pre[s + 1] += s_pre[s];
+  if (a.dloc) {
+    // gradient coefficients Dx, Dy, Dz in the real packing of L (degrees < p)
+    const int nd = a.p * a.p;
+    for (int k = lane; k < nd; k += 64) {
+      int j = 0;
+      while ((j + 1) * (j + 1) <= k) ++j;
+      const int r = k - j * j;  // 0 -> m = 0; then (m, re), (m, im) pairs
+      const int b = (r + 1) >> 1;
+      const bool imag = r > 0 && (r & 1) == 0;
+      T xr, xi, yr, yi, zr, zi;
+      grad_coeffs(loc, j, b, xr, xi, yr, yi, zr, zi);
+      loc[a.K + k] = imag ? xi : xr;
+      loc[2 * a.K + k] = imag ? yi : yr;
+      loc[3 * a.K + k] = imag ? zi : zr;
+    }
   }
   __syncthreads();
 
   const Geom g = *gp;
   const double h = g.edge / n, inv_h = 1.0 / h, half = 0.5 * g.edge;
   const double c_r2 = a.periodic ? 2.0 * 3.14159265358979323846 / (3.0 * g.edge * g.edge * g.edge) : 0.0;
-  const T cen0 = T(-0.5) - T(0.5) * BW;  // slot s has centre s + cen0 (block-centred leaf units)
-  const int tbeg = t_start[0], tend = t_start[BL];
-  const int total = s_pre[NS];
+  const int tb = nb_st[13], nt_leaf = nb_ct[13];
+  const T *Dx = loc + a.K, *Dy = Dx + a.K, *Dz = Dy + a.K;
   double esum = 0.0;
-
-  for (int t0 = tbeg; t0 < tend; t0 += blockDim.x) {
-    const int ti = t0 + tid;
-    const bool valid = ti < tend;
-    Atom4<T> me = {T(0), T(0), T(0), T(0)};
-    int my = 0;
-    if (valid) {
-      me = sorted[ti];
-      for (int b = 1; b < BL; ++b)
-        if (ti >= t_start[b]) my = b;
-    }
-    const int lx = BW == 2 ? (my >> 2) & 1 : 0, ly = BW == 2 ? (my >> 1) & 1 : 0, lz = BW == 2 ? my & 1 : 0;
-    const T px = me.x + (T)(lx + 1) + cen0, py = me.y + (T)(ly + 1) + cen0, pz = me.z + (T)(lz + 1) + cen0;
-    T phi = T(0), ex = T(0), ey = T(0), ez = T(0);
-    for (int c0 = 0; c0 < total; c0 += a.cap) {
-      const int c1 = min(total, c0 + a.cap);
-      __syncthreads();
-      for (int e = tid; e < c1 - c0; e += blockDim.x) {
-        const int gi = c0 + e;
-        int lo = 0, hi = NS - 1;  // slot s with s_pre[s] <= gi < s_pre[s+1]
-        while (lo < hi) {
-          const int mid = (lo + hi + 1) >> 1;
-          if (s_pre[mid] <= gi) lo = mid;
-          else hi = mid - 1;
-        }
-        const int s = lo;
-        const Atom4<T> at = sorted[s_start[s] + gi - s_pre[s]];
-        const int sx = s / (SW * SW), sy = (s / SW) % SW, sz = s % SW;
-        Atom4<T> o;
-        o.x = at.x + (T)sx + cen0;
-        o.y = at.y + (T)sy + cen0;
-        o.z = at.z + (T)sz + cen0;
-        o.q = at.q;
-        src[e] = o;
-      }
-      __syncthreads();
-      if (valid) {
-        for (int dx = 0; dx < 3; ++dx)
-          for (int dy = 0; dy < 3; ++dy)
-            for (int dz = 0; dz < 3; ++dz) {
-              const int s = ((lx + dx) * SW + (ly + dy)) * SW + (lz + dz);
-              const int j0 = max(s_pre[s], c0) - c0, j1 = min(s_pre[s + 1], c1) - c0;
-              for (int j = j0; j < j1; ++j) {
-                const Atom4<T> o = src[j];
-                const T rx = px - o.x, ry = py - o.y, rz = pz - o.z;
-                const T r2 = rx * rx + ry * ry + rz * rz;
-                const T ri = r2 > T(0) ? rsqrt_t<T>(r2) : T(0);
-                const T qr = o.q * ri;
-                phi += qr;
-                const T f = qr * ri * ri;
-                ex += f * rx;
-                ey += f * ry;
-                ez += f * rz;
-              }
-            }
-      }
-    }
-    if (valid) {
-      const T *Lm = loc + my * a.K;
+  for (int tp = tb; tp < tb + nt_leaf; tp += 64) {
+    const int nt = min(64, tb + nt_leaf - tp);
+    int M;
+    const P2PPass ps = p2p_pass_shape(nt, M);
+    T acc[4] = {T(0), T(0), T(0), T(0)};
+    if (M == 1) p2p_wave<T, 1>(sorted, nb_st, nb_ct, tp, nt, lane, ps, acc);
+    else if (M == 2) p2p_wave<T, 2>(sorted, nb_st, nb_ct, tp, nt, lane, ps, acc);
+    else p2p_wave<T, 3>(sorted, nb_st, nb_ct, tp, nt, lane, ps, acc);
+    if (lane < nt) {
+      const int ti = tp + lane;
+      const Atom4<T> me = sorted[ti];
       T pf = T(0), gx = T(0), gy = T(0), gz = T(0);
       const int p = a.p;
-      for_regular(p, me.x, me.y, me.z, [&](int nn, int m, T re, T im) {
-        const int i0 = ridx_d(nn, m, 0);
-        const T w = m ? T(2) : T(1);
-        pf += w * (Lm[i0] * re + (m ? Lm[i0 + 1] * im : T(0)));
-        if (nn < p) {
-          T xr, xi, yr, yi, zr, zi;
-          grad_coeffs(Lm, nn, m, xr, xi, yr, yi, zr, zi);
-          gx += w * (xr * re + xi * im);
-          gy += w * (yr * re + yi * im);
-          gz += w * (zr * re + zi * im);
-        }
-      });
-      double ph = ((double)phi + (double)pf) * inv_h;
-      double E[3] = {((double)ex - (double)gx) * inv_h * inv_h, ((double)ey - (double)gy) * inv_h * inv_h,
-                     ((double)ez - (double)gz) * inv_h * inv_h};
+      if (a.dloc) {
+        for_regular(p, me.x, me.y, me.z, [&](int nn, int m, T re, T im) {
+          const int i0 = ridx_d(nn, m, 0);
+          if (m) {
+            pf += T(2) * (loc[i0] * re + loc[i0 + 1] * im);
+            if (nn < p) {
+              gx += T(2) * (Dx[i0] * re + Dx[i0 + 1] * im);
+              gy += T(2) * (Dy[i0] * re + Dy[i0 + 1] * im);
+              gz += T(2) * (Dz[i0] * re + Dz[i0 + 1] * im);
+            }
+          } else {
+            pf += loc[i0] * re;
+            if (nn < p) {
+              gx += Dx[i0] * re;
+              gy += Dy[i0] * re;
+              gz += Dz[i0] * re;
+            }
+          }
+        });
+      } else {
+        for_regular(p, me.x, me.y, me.z, [&](int nn, int m, T re, T im) {
+          const int i0 = ridx_d(nn, m, 0);
+          const T w = m ? T(2) : T(1);
+          pf += w * (loc[i0] * re + (m ? loc[i0 + 1] * im : T(0)));
+          if (nn < p) {
+            T xr, xi, yr, yi, zr, zi;
+            grad_coeffs(loc, nn, m, xr, xi, yr, yi, zr, zi);
+            gx += w * (xr * re + xi * im);
+            gy += w * (yr * re + yi * im);
+            gz += w * (zr * re + zi * im);
+          }
+        });
+      }
+      double ph = ((double)acc[0] + (double)pf) * inv_h;
+      double E[3] = {((double)acc[1] - (double)gx) * inv_h * inv_h, ((double)acc[2] - (double)gy) * inv_h * inv_h,
+                     ((double)acc[3] - (double)gz) * inv_h * inv_h};
       if (a.periodic) {
-        const double ax = (b0x + lx + 0.5 + (double)me.x) * h - half;
-        const double ay = (b0y + ly + 0.5 + (double)me.y) * h - half;
-        const double az = (b0z + lz + 0.5 + (double)me.z) * h - half;
+        const double ax = (bx + 0.5 + (double)me.x) * h - half;
+        const double ay = (by + 0.5 + (double)me.y) * h - half;
+        const double az = (bz + 0.5 + (double)me.z) * h - half;
         ph += c_r2 * (g.Q * (ax * ax + ay * ay + az * az) - 2.0 * (g.D[0] * ax + g.D[1] * ay + g.D[2] * az) + g.S2);
         E[0] += 2.0 * c_r2 * (g.D[0] - g.Q * ax);
         E[1] += 2.0 * c_r2 * (g.D[1] - g.Q * ay);
@@ -956,13 +1059,7 @@ __global__ void __launch_bounds__(256) k_p2p_l2p(const Atom4<T> *__restrict__ so
     }
   }
   for (int off = 32; off > 0; off >>= 1) esum += __shfl_xor(esum, off);
-  if ((tid & 63) == 0) s_red[tid >> 6] = esum;
-  __syncthreads();
-  if (tid == 0) {
-    double s = 0.0;
-    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) s += s_red[w];
-    epart[blockIdx.x] = s;
-  }
+  if (lane == 0) epart[leaf] = esum;
 }
 
 // ---------------------------------------------------------------------------
@@ -1424,7 +1521,7 @@ void launch_mfma_probe(const T *A, const T *B, T *C, int rows, int kk, hipStream
 
 template <class T>
 int p2p_blocks(int d) {
-  return d >= 1 ? 1 << (3 * (d - 1)) : 1;
+  return 1 << (3 * d);  // one block per leaf
 }
 
 template <class T>
@@ -1437,9 +1534,11 @@ void launch_p2p(const Atom4<T> *sorted, const int *start, const int *perm, const
   a.p = p;
   a.K = (p + 1) * (p + 1);
   a.ke = ke;
-  a.cap = (int)(40960 / sizeof(Atom4<T>));
-  const size_t lds = a.cap * sizeof(Atom4<T>) + (size_t)8 * a.K * sizeof(T);
-  hipLaunchKernelGGL(k_p2p_l2p<T>, dim3(p2p_blocks<T>(d)), dim3(256), lds, st, sorted, start, perm, Lleaf, g, a,
+  a.cap = 0;
+  // gradient coefficients in LDS when L, Dx, Dy, Dz fit in 16 KB
+  a.dloc = (size_t)4 * a.K * sizeof(T) <= 16384 ? 1 : 0;
+  const size_t lds = (size_t)(a.dloc ? 4 : 1) * a.K * sizeof(T);
+  hipLaunchKernelGGL(k_p2p_l2p<T>, dim3(p2p_blocks<T>(d)), dim3(64), lds, st, sorted, start, perm, Lleaf, g, a,
                      phi_sorted, F, pot_user, epart);
 }
 

@@ -27,7 +27,7 @@ struct XArgs {
 };
 
 struct P2PArgs {
-  int d, periodic, p, K, KS, cap;
+  int d, periodic, p, K, KS, cap, dloc;
   double ke;
 };
 
