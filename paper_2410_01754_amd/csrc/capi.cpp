@@ -53,7 +53,7 @@ struct mahi_ctx {
   void *Mc = nullptr, *Lc = nullptr, *m2l = nullptr, *m2m = nullptr, *l2l = nullptr, *sorted = nullptr;
   double *LamT = nullptr, *qds = nullptr, *epart = nullptr, *dE_site = nullptr, *dvdl = nullptr, *E = nullptr;
   double *bbox = nullptr, *lam = nullptr, *fq = nullptr;
-  int4 *lists = nullptr, *child_ops = nullptr;
+  int4 *lists = nullptr;
   Geom *geom = nullptr;
   int *key = nullptr, *count = nullptr, *start = nullptr, *cursor = nullptr, *tmp = nullptr, *perm = nullptr,
       *slot_of = nullptr;
@@ -179,34 +179,27 @@ mahi_status setup_device(mahi_ctx *ctx, const std::vector<double> &q_env, const 
     for (int64_t i = 0; i < N; ++i) qh[i] = (T)q_env[i];
     HIP_TRY(hipMemcpy(ctx->qt, qh.data(), sizeof(T) * N, hipMemcpyHostToDevice), "upload charges");
   }
-  // translation tables, in the matrix-core layout [op][k (padded)][row (padded)]
+  // M2L table layout of k_xlate (float64): [op][k (padded)][row (padded)]
   int KK, RP;
   m2l_table_layout<T>(p, KK, RP);
-  auto to_mfma = [&](const std::vector<double> &rowmajor, T *dst) {
-    for (int r = 0; r < K; ++r)
-      for (int c = 0; c < K; ++c) dst[(size_t)c * RP + r] = (T)rowmajor[(size_t)r * K + c];
-  };
   {
-    std::vector<double> Tm((size_t)K * K);
-    std::vector<T> up((size_t)8 * KK * RP, T(0)), dn((size_t)8 * KK * RP, T(0));
+    // child c of a parent sits at offset delta_c (parent units); stacks A[c][k][r] for k_updown
+    std::vector<std::vector<double>> Tup(8, std::vector<double>((size_t)K * K)), Tdn(8, std::vector<double>((size_t)K * K));
+    const double *pu[8], *pd[8];
     for (int s = 0; s < 8; ++s) {
       const double delta[3] = {(((s >> 2) & 1) - 0.5) * 0.5, (((s >> 1) & 1) - 0.5) * 0.5, ((s & 1) - 0.5) * 0.5};
-      m2m_matrix(p, delta, Tm.data());
-      to_mfma(Tm, up.data() + (size_t)s * KK * RP);
-      l2l_matrix(p, delta, Tm.data());
-      to_mfma(Tm, dn.data() + (size_t)s * KK * RP);
+      m2m_matrix(p, delta, Tup[s].data());
+      l2l_matrix(p, delta, Tdn[s].data());
+      pu[s] = Tup[s].data();
+      pd[s] = Tdn[s].data();
     }
+    std::vector<T> up((size_t)8 * K * KS), dn((size_t)8 * K * KS);
+    updown_table<T>(K, KS, pu, up.data());
+    updown_table<T>(K, KS, pd, dn.data());
     HIP_TRY(ctx->alloc(ctx->m2m, sizeof(T) * up.size()), "alloc m2m");
     HIP_TRY(ctx->alloc(ctx->l2l, sizeof(T) * dn.size()), "alloc l2l");
     HIP_TRY(hipMemcpy(ctx->m2m, up.data(), sizeof(T) * up.size(), hipMemcpyHostToDevice), "upload m2m");
     HIP_TRY(hipMemcpy(ctx->l2l, dn.data(), sizeof(T) * dn.size(), hipMemcpyHostToDevice), "upload l2l");
-    std::vector<int4> child(8);
-    for (int c = 0; c < 8; ++c) {
-      child[c].x = child[c].y = child[c].z = 0;
-      child[c].w = c;
-    }
-    HIP_TRY(ctx->alloc(ctx->child_ops, sizeof(int4) * 8), "alloc child ops");
-    HIP_TRY(hipMemcpy(ctx->child_ops, child.data(), sizeof(int4) * 8, hipMemcpyHostToDevice), "upload child ops");
   }
   const int lmin = ctx->periodic ? 1 : 2;
   if (d >= lmin) {
@@ -309,8 +302,7 @@ mahi_status eval_impl(mahi_ctx *ctx, const mahi_eval_args *a) {
   ctx->mark(2);
   const int lmin = ctx->periodic ? 1 : 2;
   const int mlow = ctx->periodic ? 0 : 2;
-  for (int l = d - 1; l >= mlow; --l)
-    launch_xlate_m2m<T>(Mc, l, static_cast<const T *>(ctx->m2m), ctx->child_ops, p, KS, st);
+  for (int l = d - 1; l >= mlow; --l) launch_updown<T>(Mc, static_cast<const T *>(ctx->m2m), p, KS, l, true, st);
   ctx->mark(3);
   if (ctx->periodic) launch_lattice<T>(Mc, Lc, ctx->LamT, ncoef(p), ctx->qds, nleaf, ctx->geom, st);
   ctx->mark(4);
@@ -323,7 +315,7 @@ mahi_status eval_impl(mahi_ctx *ctx, const mahi_eval_args *a) {
   }
   ctx->mark(5);
   for (int l = ctx->periodic ? 1 : 3; l <= d; ++l)
-    launch_xlate_l2l<T>(Lc, l, static_cast<const T *>(ctx->l2l), ctx->child_ops, p, KS, st);
+    launch_updown<T>(Lc, static_cast<const T *>(ctx->l2l), p, KS, l - 1, false, st);
   ctx->mark(6);
   launch_p2p<T>(tb.sorted, ctx->start, ctx->perm, Lc + level_offset(d) * KS, KS, ctx->geom, d, ctx->periodic, p, ctx->ke,
                 static_cast<T *>(ctx->phi_sorted), F, pot, ctx->epart, st);

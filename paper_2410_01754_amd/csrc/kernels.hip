@@ -180,20 +180,34 @@ __global__ void k_bbox_final(const double *__restrict__ part, int nblk, Geom *g)
 // ---------------------------------------------------------------------------
 // Octree build: counting sort of atoms by Morton leaf index
 // ---------------------------------------------------------------------------
+// Position of atom i inside the cell (w, wrapped when periodic) and its leaf
+// cell c.  Divisions are replaced by products with reciprocals; an atom on a
+// cell face may land in either neighbour, which the clamped leaf-local
+// coordinates tolerate.
 template <class T>
 __device__ __forceinline__ void locate(const T *xyz, int64_t i, const Geom &g, int periodic, int n, double w[3], int c[3]) {
-  const double h = g.edge / n;
+  const double inv_edge = 1.0 / g.edge, inv_h = n * inv_edge;
   for (int d = 0; d < 3; ++d) {
     const double x = (double)xyz[3 * i + d];
-    w[d] = periodic ? wrap_coord(x, g.edge) : x - g.origin[d];
-    int ci = (int)floor(w[d] / h);
+    double u;
+    if (periodic) {
+      u = x - g.edge * floor(x * inv_edge);
+      if (u >= g.edge) u -= g.edge;
+      if (u < 0.0) u = 0.0;
+    } else {
+      u = x - g.origin[d];
+    }
+    w[d] = u;
+    const int ci = (int)floor(u * inv_h);
     c[d] = ci < 0 ? 0 : (ci >= n ? n - 1 : ci);
   }
 }
 
+// Leaf key of every atom and its arrival rank within the leaf (the order of
+// equal keys is fixed later by k_leafsort).
 template <class T>
 __global__ void k_bin(const T *__restrict__ xyz, int64_t n_atoms, const Geom *__restrict__ gp, int d, int periodic,
-                      int *__restrict__ key, int *__restrict__ count) {
+                      int *__restrict__ key, int *__restrict__ rank, int *__restrict__ count) {
   const Geom g = *gp;
   const int n = 1 << d;
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n_atoms; i += (int64_t)gridDim.x * blockDim.x) {
@@ -202,41 +216,66 @@ __global__ void k_bin(const T *__restrict__ xyz, int64_t n_atoms, const Geom *__
     locate(xyz, i, g, periodic, n, w, c);
     const int k = (int)morton(c[0], c[1], c[2]);
     key[i] = k;
-    atomicAdd(&count[k], 1);
+    rank[i] = atomicAdd(&count[k], 1);
   }
 }
 
-// Exclusive scan of leaf counts (one block of 1024 threads); also seeds the scatter cursors.
-__global__ void __launch_bounds__(1024) k_scan(const int *__restrict__ count, int *__restrict__ start,
-                                               int *__restrict__ cursor, int nleaf) {
-  __shared__ int part[1024];
-  const int t = threadIdx.x;
-  const int per = (nleaf + 1023) / 1024;
-  const int b = t * per, e = min(nleaf, b + per);
-  int s = 0;
-  for (int i = b; i < e; ++i) s += count[i];
-  part[t] = s;
-  __syncthreads();
-  for (int off = 1; off < 1024; off <<= 1) {
-    int v = (t >= off) ? part[t - off] : 0;
+// Exclusive scan of leaf counts in one block of 1024 threads: rounds of 8192
+// counts are loaded coalesced into LDS, each thread scans 8 consecutive ones,
+// the block scans the thread sums (wave scans, then the 16 wave sums) and the
+// round's total carries into the next round.  start[nleaf] receives the total.
+__global__ void __launch_bounds__(1024) k_scan(const int *__restrict__ count, int *__restrict__ start, int nleaf) {
+  constexpr int R = 8192, PER = 8;
+  __shared__ int buf[R + R / 32];  // padded: element i at i + i / 32
+  __shared__ int wsum[16];
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+  int carry = 0;
+  for (int r0 = 0; r0 < nleaf; r0 += R) {
+    const int nr = min(R, nleaf - r0);
+    for (int i = t; i < R; i += 1024) buf[i + i / 32] = i < nr ? count[r0 + i] : 0;
     __syncthreads();
-    part[t] += v;
+    int v[PER], loc = 0;
+#pragma unroll
+    for (int k = 0; k < PER; ++k) {
+      const int i = t * PER + k;
+      v[k] = buf[i + i / 32];
+      loc += v[k];
+    }
+    int s = loc;
+    for (int o = 1; o < 64; o <<= 1) {
+      const int u = __shfl_up(s, o, 64);
+      if (lane >= o) s += u;
+    }
+    if (lane == 63) wsum[wave] = s;
+    __syncthreads();
+    if (wave == 0) {
+      int w = lane < 16 ? wsum[lane] : 0;
+      for (int o = 1; o < 16; o <<= 1) {
+        const int u = __shfl_up(w, o, 64);
+        if (lane >= o) w += u;
+      }
+      if (lane < 16) wsum[lane] = w;  // inclusive wave prefix
+    }
+    __syncthreads();
+    int run = carry + s - loc + (wave > 0 ? wsum[wave - 1] : 0);
+#pragma unroll
+    for (int k = 0; k < PER; ++k) {
+      const int i = t * PER + k;
+      buf[i + i / 32] = run;
+      run += v[k];
+    }
+    carry += wsum[15];
+    __syncthreads();
+    for (int i = t; i < nr; i += 1024) start[r0 + i] = buf[i + i / 32];
     __syncthreads();
   }
-  int run = part[t] - s;
-  for (int i = b; i < e; ++i) {
-    start[i] = run;
-    cursor[i] = run;
-    run += count[i];
-  }
-  if (t == 1023) start[nleaf] = part[1023];
+  if (t == 0) start[nleaf] = carry;
 }
 
-__global__ void k_scatter(const int *__restrict__ key, int *__restrict__ cursor, int *__restrict__ tmp, int64_t n_atoms) {
-  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n_atoms; i += (int64_t)gridDim.x * blockDim.x) {
-    const int slot = atomicAdd(&cursor[key[i]], 1);
-    tmp[slot] = (int)i;
-  }
+__global__ void k_scatter(const int *__restrict__ key, const int *__restrict__ rank, const int *__restrict__ start,
+                          int *__restrict__ tmp, int64_t n_atoms) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n_atoms; i += (int64_t)gridDim.x * blockDim.x)
+    tmp[start[key[i]] + rank[i]] = (int)i;
 }
 
 // One wave per leaf: order the leaf's atoms by original index (deterministic
@@ -253,12 +292,17 @@ __global__ void __launch_bounds__(256) k_leafsort(const int *__restrict__ tmp, c
   if (leaf >= nleaf) return;
   const Geom g = *gp;
   const int n = 1 << d;
-  const double h = g.edge / n;
+  const double inv_h = n / g.edge;
   const int s0 = start[leaf], cnt = start[leaf + 1] - s0;
   for (int a = lane; a < cnt; a += 64) {
     const int me = tmp[s0 + a];
     int rank = 0;
-    for (int b = 0; b < cnt; ++b) rank += (tmp[s0 + b] < me) ? 1 : 0;
+    if (cnt <= 64) {
+      // every atom of the leaf is held by one lane: compare through cross-lane reads
+      for (int b = 0; b < cnt; ++b) rank += (__shfl(me, b, 64) < me) ? 1 : 0;
+    } else {
+      for (int b = 0; b < cnt; ++b) rank += (tmp[s0 + b] < me) ? 1 : 0;
+    }
     const int slot = s0 + rank;
     perm[slot] = me;
     slot_of[me] = slot;
@@ -266,9 +310,9 @@ __global__ void __launch_bounds__(256) k_leafsort(const int *__restrict__ tmp, c
     int c[3];
     locate(xyz, me, g, periodic, n, w, c);
     Atom4<T> at;
-    at.x = (T)(w[0] / h - (c[0] + 0.5));
-    at.y = (T)(w[1] / h - (c[1] + 0.5));
-    at.z = (T)(w[2] / h - (c[2] + 0.5));
+    at.x = (T)(w[0] * inv_h - (c[0] + 0.5));
+    at.y = (T)(w[1] * inv_h - (c[1] + 0.5));
+    at.z = (T)(w[2] * inv_h - (c[2] + 0.5));
     at.q = qt[me];
     sorted[slot] = at;
   }
@@ -345,19 +389,33 @@ __global__ void __launch_bounds__(64) k_p2m(const Atom4<T> *__restrict__ sorted,
 // float64 charge moments Q, D, S2 of the r^2 part of the lattice remainder.
 // ---------------------------------------------------------------------------
 template <class T>
-__global__ void __launch_bounds__(256) k_lattice(const T *__restrict__ M, T *__restrict__ L,
-                                                 const double *__restrict__ LamT, int K,
-                                                 const double *__restrict__ qds, int nleaf, Geom *g) {
-  __shared__ double red[5][256];
+__global__ void __launch_bounds__(1024) k_lattice(const T *__restrict__ M, T *__restrict__ L,
+                                                  const double *__restrict__ LamT, int K,
+                                                  const double *__restrict__ qds, int nleaf, Geom *g) {
+  __shared__ double red[5][1024];
   __shared__ double mroot[(kMaxOrder + 1) * (kMaxOrder + 1)];
+  __shared__ double rowp[4][(kMaxOrder + 1) * (kMaxOrder + 1)];
   const int t = threadIdx.x;
+  // charge moments: thread t sums leaves t, t + 1024, ... (eight in flight), then a fixed tree
   double v[5] = {0, 0, 0, 0, 0};
-  for (int l = t; l < nleaf; l += 256)
+  int l = t;
+  for (; l + 7 * 1024 < nleaf; l += 8 * 1024) {
+    double r[8][5];
+#pragma unroll
+    for (int u = 0; u < 8; ++u)
+#pragma unroll
+      for (int k = 0; k < 5; ++k) r[u][k] = qds[(int64_t)(l + u * 1024) * 5 + k];
+#pragma unroll
+    for (int u = 0; u < 8; ++u)
+#pragma unroll
+      for (int k = 0; k < 5; ++k) v[k] += r[u][k];
+  }
+  for (; l < nleaf; l += 1024)
     for (int k = 0; k < 5; ++k) v[k] += qds[(int64_t)l * 5 + k];
   for (int k = 0; k < 5; ++k) red[k][t] = v[k];
-  for (int c = t; c < K; c += 256) mroot[c] = (double)M[c];
+  for (int c = t; c < K; c += 1024) mroot[c] = (double)M[c];
   __syncthreads();
-  for (int w = 128; w > 0; w >>= 1) {
+  for (int w = 512; w > 0; w >>= 1) {
     if (t < w)
       for (int k = 0; k < 5; ++k) red[k][t] += red[k][t + w];
     __syncthreads();
@@ -369,22 +427,21 @@ __global__ void __launch_bounds__(256) k_lattice(const T *__restrict__ M, T *__r
     g->D[2] = red[3][0];
     g->S2 = red[4][0];
   }
-  for (int r = t; r < K; r += 256) {
+  // root local = Lambda M_root: row r, column quarter q in thread (q, r); quarters summed in order
+  const int q = t >> 8;
+  for (int r = t & 255; r < K; r += 256) {
+    const int c0 = q * K / 4, c1 = (q + 1) * K / 4;
     double acc = 0.0;
-    for (int c = 0; c < K; ++c) acc += LamT[(int64_t)c * K + r] * mroot[c];
-    L[r] = (T)acc;
+    for (int c = c0; c < c1; ++c) acc += LamT[(int64_t)c * K + r] * mroot[c];
+    rowp[q][r] = acc;
   }
+  __syncthreads();
+  for (int rr = t; rr < K; rr += 1024) L[rr] = (T)(((rowp[0][rr] + rowp[1][rr]) + rowp[2][rr]) + rowp[3][rr]);
 }
 
 // ---------------------------------------------------------------------------
-// M2L on the matrix cores.
-// For a level, a parity class c (position of the target inside its parent)
-// has one fixed list of 189 source offsets v.  A block takes 64 targets of one
-// class (children c of 64 consecutive parents) and one group of 32-row (f32) or
-// 16-row (f64) output tiles; for every v it stages the 64 gathered source
-// multipoles in LDS (B operand, K x 64) and multiplies with the dense operator
-// T_v (A operand, rows x K, read from the table in L2) on MFMA tiles:
-//   L_t (rows x 64) += T_v (rows x K) * [M_{t-v}] (K x 64).
+// Matrix-core tile conventions (lane layouts of the A, B and D fragments) of
+// the MFMA instructions used by the translation kernels.
 // ---------------------------------------------------------------------------
 typedef float floatx16 __attribute__((ext_vector_type(16)));
 typedef double doublex4 __attribute__((ext_vector_type(4)));
@@ -759,6 +816,79 @@ __global__ void k_m2l_reduce(const floatx4 *__restrict__ part, floatx4 *__restri
     floatx4 s = part[i];
     for (int k = 1; k < nsplit; ++k) s += part[i + k * stride];
     L[i] = s;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// M2M and L2L as stacked dense products on the vector ALU.
+// The 8 children of parent P are the consecutive boxes 8P .. 8P+7 one level
+// down, so for a block of NP parents:
+//   M2M: M[P] = sum_c T_c M[8P + c]          (T_c: child c -> parent)
+//   L2L: L[8P + c] += S_c L[P]                (S_c: parent -> child c)
+// Thread (c, r) owns output row r of the child-c product for all NP parents;
+// the operator element A[c][k][r] (row r fastest: coalesced) is read once and
+// used for the NP parents, whose input rows sit in LDS (read as broadcasts).
+// M2M sums the 8 child partials in child order through LDS; L2L adds its
+// result to the child's local expansion in place (one writer per element).
+// ---------------------------------------------------------------------------
+template <class T, bool UP, int NP>
+__global__ void __launch_bounds__(1024) k_updown(T *__restrict__ X, const T *__restrict__ A, int K, int KS,
+                                                 int64_t off_parent, int64_t off_child, int64_t nparent) {
+  extern __shared__ unsigned char smem_raw[];
+  // inputs transposed so that the NP parents of one (c, k) are contiguous:
+  //   UP: xs[c][k][NP] (children);  down: xs[k][NP] (parents)
+  T *xs = reinterpret_cast<T *>(smem_raw);
+  T *part = xs + (size_t)(UP ? 8 : 1) * KS * NP;  // UP: [NP][8][KS] child partials
+  const int64_t P0 = (int64_t)blockIdx.x * NP;
+  const int np = (int)min((int64_t)NP, nparent - P0);
+  const int in_len = UP ? 8 * KS : KS;
+  {
+    const T *src = UP ? X + (off_child + 8 * P0) * KS : X + (off_parent + P0) * KS;
+    for (int e = threadIdx.x; e < NP * in_len; e += blockDim.x) {
+      const int p = e / in_len, q = e - p * in_len;
+      xs[q * NP + p] = p < np ? src[e] : T(0);
+    }
+  }
+  __syncthreads();
+  const int nrow = 8 * KS;  // (c, r) pairs
+  for (int cr = threadIdx.x; cr < nrow; cr += blockDim.x) {
+    const int c = cr / KS, r = cr - c * KS;
+    T acc[NP];
+#pragma unroll
+    for (int p = 0; p < NP; ++p) acc[p] = T(0);
+    const T *Ac = A + (int64_t)c * K * KS + r;
+    const T *xc = xs + (UP ? c * KS * NP : 0);
+    constexpr int KB = NP >= 8 ? 32 : 16;  // operator elements in flight
+    for (int k0 = 0; k0 < K; k0 += KB) {
+      T av[KB];
+#pragma unroll
+      for (int u = 0; u < KB; ++u) av[u] = k0 + u < K ? Ac[(int64_t)(k0 + u) * KS] : T(0);
+#pragma unroll
+      for (int u = 0; u < KB; ++u) {
+        if (k0 + u < K) {
+          const T *xk = xc + (k0 + u) * NP;
+#pragma unroll
+          for (int p = 0; p < NP; ++p) acc[p] += av[u] * xk[p];
+        }
+      }
+    }
+    if (UP) {
+#pragma unroll
+      for (int p = 0; p < NP; ++p) part[(p * 8 + c) * KS + r] = acc[p];
+    } else {
+#pragma unroll
+      for (int p = 0; p < NP; ++p)
+        if (p < np && r < K) X[(off_child + 8 * (P0 + p) + c) * KS + r] += acc[p];
+    }
+  }
+  if (UP) {
+    __syncthreads();
+    for (int e = threadIdx.x; e < np * KS; e += blockDim.x) {
+      const int p = e / KS, r = e - p * KS;
+      T s = T(0);
+      for (int c = 0; c < 8; ++c) s += part[(p * 8 + c) * KS + r];
+      if (r < K) X[(off_parent + P0 + p) * KS + r] = s;
+    }
   }
 }
 
@@ -1272,20 +1402,30 @@ __global__ void __launch_bounds__(64) k_site(SiteArgs a, const T *__restrict__ x
 }
 
 // E = ke (1/2 sum_blocks epart + sum_sites dE), fixed order.
-__global__ void __launch_bounds__(256) k_finalize(const double *__restrict__ epart, int nb,
-                                                  const double *__restrict__ dE_site, int ns, double ke,
-                                                  double *__restrict__ E) {
-  __shared__ double s[256];
+__global__ void __launch_bounds__(1024) k_finalize(const double *__restrict__ epart, int nb,
+                                                   const double *__restrict__ dE_site, int ns, double ke,
+                                                   double *__restrict__ E) {
+  __shared__ double s[1024];
+  const int t = threadIdx.x;
+  // fixed-order partial sums: thread t adds entries t, t + 1024, ... (loads unrolled 8-fold)
   double v = 0.0, w = 0.0;
-  for (int i = threadIdx.x; i < nb; i += 256) v += epart[i];
-  for (int i = threadIdx.x; i < ns; i += 256) w += dE_site[i];
-  s[threadIdx.x] = 0.5 * v + w;
+  int i = t;
+  for (; i + 7 * 1024 < nb; i += 8 * 1024) {
+    double r[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) r[k] = epart[i + k * 1024];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) v += r[k];
+  }
+  for (; i < nb; i += 1024) v += epart[i];
+  for (int k = t; k < ns; k += 1024) w += dE_site[k];
+  s[t] = 0.5 * v + w;
   __syncthreads();
-  for (int k = 128; k > 0; k >>= 1) {
-    if ((int)threadIdx.x < k) s[threadIdx.x] += s[threadIdx.x + k];
+  for (int k = 512; k > 0; k >>= 1) {
+    if (t < k) s[t] += s[t + k];
     __syncthreads();
   }
-  if (threadIdx.x == 0) *E = ke * s[0];
+  if (t == 0) *E = ke * s[0];
 }
 
 // ---------------------------------------------------------------------------
@@ -1312,10 +1452,12 @@ template <class T>
 void launch_tree(const T *xyz, const T *qt, int64_t n, const Geom *g, int d, int periodic, TreeBufs<T> b,
                  hipStream_t st) {
   const int nleaf = 1 << (3 * d);
+  // slot_of holds the in-leaf arrival ranks until k_leafsort writes the slots
   launch_fill_i32(b.count, 0, nleaf, st);
-  hipLaunchKernelGGL(k_bin<T>, dim3(grid_for(n, 256)), dim3(256), 0, st, xyz, n, g, d, periodic, b.key, b.count);
-  hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, st, b.count, b.start, b.cursor, nleaf);
-  hipLaunchKernelGGL(k_scatter, dim3(grid_for(n, 256)), dim3(256), 0, st, b.key, b.cursor, b.tmp, n);
+  hipLaunchKernelGGL(k_bin<T>, dim3(grid_for(n, 256)), dim3(256), 0, st, xyz, n, g, d, periodic, b.key, b.slot_of,
+                     b.count);
+  hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, st, b.count, b.start, nleaf);
+  hipLaunchKernelGGL(k_scatter, dim3(grid_for(n, 256)), dim3(256), 0, st, b.key, b.slot_of, b.start, b.tmp, n);
   hipLaunchKernelGGL(k_leafsort<T>, dim3((nleaf + 3) / 4), dim3(256), 0, st, b.tmp, b.start, nleaf, xyz, qt, g, d,
                      periodic, b.perm, b.slot_of, b.sorted);
 }
@@ -1333,7 +1475,7 @@ void launch_p2m(const Atom4<T> *sorted, const int *start, int nleaf, int p, int 
 
 template <class T>
 void launch_lattice(const T *M, T *L, const double *LamT, int K, const double *qds, int nleaf, Geom *g, hipStream_t st) {
-  hipLaunchKernelGGL(k_lattice<T>, dim3(1), dim3(256), 0, st, M, L, LamT, K, qds, nleaf, g);
+  hipLaunchKernelGGL(k_lattice<T>, dim3(1), dim3(1024), 0, st, M, L, LamT, K, qds, nleaf, g);
 }
 
 // Operator tables: [slot][KK][RP], k padded with zero rows to whole chunks of
@@ -1513,6 +1655,55 @@ size_t m2l32_table_size(const M2LPlan &a, int nslots) {
   return (size_t)nslots * a.ngroups * a.nkc * (2 * a.ns) * kM2LRowGroup;
 }
 
+// Operator stack for k_updown: A[c][k][r] = T_c[r][k] (r, k < K; zero padded to KS rows).
+template <class T>
+void updown_table(int K, int KS, const double *const *Tc, T *A) {
+  for (int c = 0; c < 8; ++c)
+    for (int k = 0; k < K; ++k)
+      for (int r = 0; r < KS; ++r) A[((size_t)c * K + k) * KS + r] = r < K ? (T)Tc[c][(size_t)r * K + k] : T(0);
+}
+
+// parents per block: the largest of 8, 4, 2, 1 whose inputs (and, for M2M, child
+// partials) fit in 64 KB of LDS
+template <class T>
+int updown_np(int KS, bool up) {
+  int np = 8;
+  while (np > 1 && (size_t)np * (up ? 16 : 1) * KS * sizeof(T) > 65536) np >>= 1;
+  return np;
+}
+
+template <class T>
+size_t updown_lds(int KS, bool up) {
+  return (size_t)updown_np<T>(KS, up) * (up ? 16 : 1) * KS * sizeof(T);
+}
+
+template <class T, bool UP, int NP>
+static void updown_go(T *X, const T *A, int K, int KS, int parent_level, hipStream_t st) {
+  const int64_t nparent = int64_t(1) << (3 * parent_level);
+  const int64_t blocks = (nparent + NP - 1) / NP;
+  const int threads = std::min(1024, (8 * KS + 63) / 64 * 64);
+  const size_t lds = (size_t)NP * (UP ? 16 : 1) * KS * sizeof(T);
+  hipLaunchKernelGGL((k_updown<T, UP, NP>), dim3((unsigned)blocks), dim3(threads), lds, st, X, A, K, KS,
+                     level_offset(parent_level), level_offset(parent_level + 1), nparent);
+}
+
+template <class T, bool UP>
+static void updown_dispatch(T *X, const T *A, int K, int KS, int parent_level, hipStream_t st) {
+  switch (updown_np<T>(KS, UP)) {
+    case 8: updown_go<T, UP, 8>(X, A, K, KS, parent_level, st); break;
+    case 4: updown_go<T, UP, 4>(X, A, K, KS, parent_level, st); break;
+    case 2: updown_go<T, UP, 2>(X, A, K, KS, parent_level, st); break;
+    default: updown_go<T, UP, 1>(X, A, K, KS, parent_level, st); break;
+  }
+}
+
+template <class T>
+void launch_updown(T *X, const T *A, int p, int KS, int parent_level, bool up, hipStream_t st) {
+  const int K = (p + 1) * (p + 1);
+  if (up) updown_dispatch<T, true>(X, A, K, KS, parent_level, st);
+  else updown_dispatch<T, false>(X, A, K, KS, parent_level, st);
+}
+
 template <class T>
 void launch_mfma_probe(const T *A, const T *B, T *C, int rows, int kk, hipStream_t st) {
   using MF = Mfma<T>;
@@ -1564,7 +1755,7 @@ void launch_site(const SiteArgs &s, const T *xyz, const int *slot_of, const T *p
 }
 
 void launch_finalize(const double *epart, int nb, const double *dE_site, int ns, double ke, double *E, hipStream_t st) {
-  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(256), 0, st, epart, nb, dE_site, ns, ke, E);
+  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(1024), 0, st, epart, nb, dE_site, ns, ke, E);
 }
 
 
@@ -1579,6 +1770,9 @@ void launch_finalize(const double *epart, int nb, const double *dE_site, int ns,
   template void launch_xlate_m2l<T>(const T *, T *, const T *, const int4 *, int, int, int, int, hipStream_t);         \
   template void launch_xlate_m2m<T>(T *, int, const T *, const int4 *, int, int, hipStream_t);                        \
   template void launch_xlate_l2l<T>(T *, int, const T *, const int4 *, int, int, hipStream_t);                        \
+  template void updown_table<T>(int, int, const double *const *, T *);                                               \
+  template void launch_updown<T>(T *, const T *, int, int, int, bool, hipStream_t);                                   \
+  template size_t updown_lds<T>(int, bool);                                                                           \
   template int p2p_blocks<T>(int);                                                                                   \
   template void launch_p2p<T>(const Atom4<T> *, const int *, const int *, const T *, int, const Geom *, int, int, int, \
                               double, T *, T *, T *, double *, hipStream_t);                                         \

@@ -69,6 +69,9 @@ void launch_m2l_f32(const float *M, float *L, float *part, const float *Tab, con
                     hipStream_t st);
 void m2l32_table(const M2LPlan &a, int slot, const double *Tv, float *dst);
 size_t m2l32_table_size(const M2LPlan &a, int nslots);
+template <class T> void updown_table(int K, int KS, const double *const *Tc, T *A);
+template <class T> size_t updown_lds(int KS, bool up);
+template <class T> void launch_updown(T *X, const T *A, int p, int KS, int parent_level, bool up, hipStream_t st);
 template <class T> void launch_mfma_probe(const T *A, const T *B, T *C, int rows, int kk, hipStream_t st);
 template <class T> int p2p_blocks(int d);
 template <class T>
