@@ -90,6 +90,75 @@ __device__ __forceinline__ void for_regular(int p, T x, T y, T z, F &&f) {
   }
 }
 
+// The same recurrence for an order fixed at compile time: the coefficients
+// are compile-time constants (tables built by a constexpr constructor) and
+// the loops unroll completely, so no coefficient is loaded at run time.
+constexpr double csqrt(double x) {  // Newton iteration; compile-time use only
+  if (!(x > 0.0)) return 0.0;
+  double r = x > 1.0 ? x : 1.0;
+  for (int i = 0; i < 80; ++i) r = 0.5 * (r + x / r);
+  return r;
+}
+
+template <int P>
+struct RegCoef {
+  double sect[P + 2], up[P + 2], b1[P + 1][P + 1], b2[P + 1][P + 1];
+  constexpr RegCoef() : sect(), up(), b1(), b2() {
+    for (int m = 0; m < P + 2; ++m) {
+      sect[m] = m > 0 ? csqrt((2.0 * m - 1.0) / (2.0 * m)) : 0.0;
+      up[m] = csqrt(2.0 * m + 1.0);
+    }
+    for (int n = 0; n <= P; ++n)
+      for (int m = 0; m <= P; ++m) {
+        const double den = double(n * n - m * m);
+        b1[n][m] = (m <= n - 2) ? (2.0 * n - 1.0) / csqrt(den) : 0.0;
+        b2[n][m] = (m <= n - 2) ? csqrt(double((n - 1) * (n - 1) - m * m)) / csqrt(den) : 0.0;
+      }
+  }
+};
+template <int P>
+__device__ constexpr RegCoef<P> kRegCoef{};
+
+template <int P, class T, class F>
+__device__ __forceinline__ void for_regular_t(T x, T y, T z, F &&f) {
+  const T r2 = x * x + y * y + z * z;
+  T sr = T(1), si = T(0);
+#pragma unroll
+  for (int m = 0; m <= P; ++m) {
+    if (m > 0) {
+      const T c = -(T)kRegCoef<P>.sect[m];
+      const T nr = c * (x * sr - y * si);
+      const T ni = c * (x * si + y * sr);
+      sr = nr;
+      si = ni;
+    }
+    f(m, m, sr, si);
+    if (m < P) {
+      T r1r = (T)kRegCoef<P>.up[m] * z * sr, r1i = (T)kRegCoef<P>.up[m] * z * si;
+      f(m + 1, m, r1r, r1i);
+      T r0r = sr, r0i = si;
+#pragma unroll
+      for (int n = m + 2; n <= P; ++n) {
+        const T b1 = (T)kRegCoef<P>.b1[n][m], b2 = (T)kRegCoef<P>.b2[n][m];
+        const T nr = b1 * z * r1r - b2 * r2 * r0r;
+        const T ni = b1 * z * r1i - b2 * r2 * r0i;
+        r0r = r1r;
+        r0i = r1i;
+        r1r = nr;
+        r1i = ni;
+        f(n, m, nr, ni);
+      }
+    }
+  }
+}
+
+// Compile-time order PT > 0, else the run-time order p.
+template <int PT, class T, class F>
+__device__ __forceinline__ void visit_regular(int p, T x, T y, T z, F &&f) {
+  if constexpr (PT > 0) for_regular_t<PT>(x, y, z, f);
+  else for_regular(p, x, y, z, f);
+}
+
 // Derivative local coefficients: for phi = sum L conj(Rt(u)), d phi / du_{x,y,z}
 // = sum D_{x,y,z} conj(Rt(u)) over degrees j < p, with each D_j^b formed from
 // L_{j+1}^{b-1}, L_{j+1}^b, L_{j+1}^{b+1} (gradient relations of the solid
@@ -321,7 +390,7 @@ __global__ void __launch_bounds__(256) k_leafsort(const int *__restrict__ tmp, c
 // ---------------------------------------------------------------------------
 // P2M: leaf multipoles; also the float64 charge moments for the lattice
 // ---------------------------------------------------------------------------
-template <class T>
+template <class T, int PT>
 __global__ void __launch_bounds__(64) k_p2m(const Atom4<T> *__restrict__ sorted, const int *__restrict__ start,
                                             int p, int K, int KS, int chunk, T *__restrict__ Mleaf, double *__restrict__ qds,
                                             const Geom *__restrict__ gp, int d) {
@@ -338,7 +407,7 @@ __global__ void __launch_bounds__(64) k_p2m(const Atom4<T> *__restrict__ sorted,
     if (lane < nch) {
       const Atom4<T> a = sorted[s0 + c0 + lane];
       T *row = rows + lane * K;
-      for_regular(p, a.x, a.y, a.z, [&](int n, int m, T re, T im) {
+      visit_regular<PT>(p, a.x, a.y, a.z, [&](int n, int m, T re, T im) {
         const int i0 = ridx_d(n, m, 0);
         row[i0] = a.q * re;
         if (m) row[i0 + 1] = -a.q * im;
@@ -701,6 +770,8 @@ k_m2l_f32(const float *__restrict__ M, float *__restrict__ Out, const float *__r
   const int64_t ntg = int64_t(1) << (3 * (l - 1));
   const int64_t P = (int64_t)chunk * kM2LTile + wave * 32 + j;
   const bool valid = P < ntg;
+  // waves whose 32 targets are all empty (levels with few boxes) skip the matrix work
+  const bool wave_busy = (int64_t)chunk * kM2LTile + wave * 32 < ntg;
   int tx = 0, ty = 0, tz = 0;
   if (valid) unmorton((uint32_t)(8 * P + cls), tx, ty, tz);
   const int64_t off = level_offset(l);
@@ -775,11 +846,13 @@ k_m2l_f32(const float *__restrict__ M, float *__restrict__ Out, const float *__r
     load_a(min(it + 2, nit - 1), ast);
     load_b(min(it + 1, nit - 1), bn);
     const float *Ar = As[buf] + h * RG + j;
+    if (wave_busy) {
 #pragma unroll
-    for (int s2 = 0; s2 < NS; ++s2) {
+      for (int s2 = 0; s2 < NS; ++s2) {
 #pragma unroll
-      for (int t = 0; t < 3; ++t)
-        acc[t] = __builtin_amdgcn_mfma_f32_32x32x2f32(Ar[2 * s2 * RG + 32 * t], bc[s2], acc[t], 0, 0, 0);
+        for (int t = 0; t < 3; ++t)
+          acc[t] = __builtin_amdgcn_mfma_f32_32x32x2f32(Ar[2 * s2 * RG + 32 * t], bc[s2], acc[t], 0, 0, 0);
+      }
     }
     __syncthreads();
   };
@@ -1055,7 +1128,7 @@ __device__ __forceinline__ void p2p_wave(const Atom4<T> *__restrict__ sorted, co
   }
 }
 
-template <class T>
+template <class T, int PT>
 __global__ void __launch_bounds__(64) k_p2p_l2p(const Atom4<T> *__restrict__ sorted, const int *__restrict__ start,
                                                 const int *__restrict__ perm, const T *__restrict__ Lleaf,
                                                 const Geom *__restrict__ gp, P2PArgs a, T *__restrict__ phi_sorted,
@@ -1130,9 +1203,9 @@ __global__ void __launch_bounds__(64) k_p2p_l2p(const Atom4<T> *__restrict__ sor
       const int ti = tp + lane;
       const Atom4<T> me = sorted[ti];
       T pf = T(0), gx = T(0), gy = T(0), gz = T(0);
-      const int p = a.p;
+      const int p = PT > 0 ? PT : a.p;
       if (a.dloc) {
-        for_regular(p, me.x, me.y, me.z, [&](int nn, int m, T re, T im) {
+        visit_regular<PT>(p, me.x, me.y, me.z, [&](int nn, int m, T re, T im) {
           const int i0 = ridx_d(nn, m, 0);
           if (m) {
             pf += T(2) * (loc[i0] * re + loc[i0 + 1] * im);
@@ -1469,8 +1542,12 @@ void launch_p2m(const Atom4<T> *sorted, const int *start, int nleaf, int p, int 
   int chunk = (int)(16384 / (K * sizeof(T)));
   if (chunk > 64) chunk = 64;
   if (chunk < 1) chunk = 1;
-  hipLaunchKernelGGL(k_p2m<T>, dim3(nleaf), dim3(64), chunk * K * sizeof(T), st, sorted, start, p, K, KS, chunk, Mleaf, qds,
-                     g, d);
+  if (p == 8)
+    hipLaunchKernelGGL((k_p2m<T, 8>), dim3(nleaf), dim3(64), chunk * K * sizeof(T), st, sorted, start, p, K, KS, chunk,
+                       Mleaf, qds, g, d);
+  else
+    hipLaunchKernelGGL((k_p2m<T, 0>), dim3(nleaf), dim3(64), chunk * K * sizeof(T), st, sorted, start, p, K, KS, chunk,
+                       Mleaf, qds, g, d);
 }
 
 template <class T>
@@ -1596,17 +1673,20 @@ void m2l32_plan(int p, int d, int periodic, int n_cu, M2LPlan &a) {
     a.ntiles += (int)(8 * ((ntg + kM2LTile - 1) / kM2LTile));
   }
   if (d + 1 <= 8) a.tiles_start[d + 1] = a.ntiles;
-  // operator ranges: choose the split count that minimises the modelled
-  // makespan with two resident blocks per CU (one item costs its operator
-  // count plus a fixed overhead; every extra partial costs a read and write)
+  // operator ranges: the split count minimising a fluid makespan model with
+  // two resident blocks per CU, in units of one operator step of a block:
+  //   max(work / slots + item / 2, item) + overhead * splits,
+  // item = 189 nkc / s steps; the overhead (prologue of an item, partial
+  // write and reduction) was fitted on the 1M-atom, depth-5 workload.
   a.nsplit = 1;
   if (a.ntiles > 0) {
     const double slots = 2.0 * (n_cu > 0 ? n_cu : 256);
+    const double work = (double)a.ntiles * a.ngroups * kListLen * a.nkc;
+    const double over = kListLen * a.nkc / 32.0;
     double best = 1e300;
     for (int s = 1; s <= kM2LMaxSplit; ++s) {
-      const double items = (double)a.ntiles * a.ngroups * s;
-      const double rounds = std::ceil(items / slots);
-      const double cost = rounds * (std::ceil((double)kListLen / s) * a.nkc + 2.0) + 0.5 * (s > 1 ? s : 0);
+      const double item = (double)kListLen * a.nkc / s;
+      const double cost = std::max(work / slots + 0.5 * item, item) + over * s;
       if (cost < best - 1e-9) {
         best = cost;
         a.nsplit = s;
@@ -1729,8 +1809,12 @@ void launch_p2p(const Atom4<T> *sorted, const int *start, const int *perm, const
   // gradient coefficients in LDS when L, Dx, Dy, Dz fit in 16 KB
   a.dloc = (size_t)4 * a.K * sizeof(T) <= 16384 ? 1 : 0;
   const size_t lds = (size_t)(a.dloc ? 4 : 1) * a.K * sizeof(T);
-  hipLaunchKernelGGL(k_p2p_l2p<T>, dim3(p2p_blocks<T>(d)), dim3(64), lds, st, sorted, start, perm, Lleaf, g, a,
-                     phi_sorted, F, pot_user, epart);
+  if (p == 8)
+    hipLaunchKernelGGL((k_p2p_l2p<T, 8>), dim3(p2p_blocks<T>(d)), dim3(64), lds, st, sorted, start, perm, Lleaf, g, a,
+                       phi_sorted, F, pot_user, epart);
+  else
+    hipLaunchKernelGGL((k_p2p_l2p<T, 0>), dim3(p2p_blocks<T>(d)), dim3(64), lds, st, sorted, start, perm, Lleaf, g, a,
+                       phi_sorted, F, pot_user, epart);
 }
 
 template <class T>
