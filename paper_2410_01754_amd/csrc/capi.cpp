@@ -50,12 +50,13 @@ struct mahi_ctx {
   // device buffers (element type T = float or double for the FMM arrays)
   void *xyz = nullptr, *qt = nullptr, *F = nullptr, *pot = nullptr, *phi_sorted = nullptr;
   void *part = nullptr;  // float32 M2L partial locals, one array per operator range
+  void *packed = nullptr;  // leaf-local atoms in input order (octree build)
   void *Mc = nullptr, *Lc = nullptr, *m2l = nullptr, *m2m = nullptr, *l2l = nullptr, *sorted = nullptr;
   double *LamT = nullptr, *qds = nullptr, *epart = nullptr, *dE_site = nullptr, *dvdl = nullptr, *E = nullptr;
   double *bbox = nullptr, *lam = nullptr, *fq = nullptr;
   int4 *lists = nullptr;
   Geom *geom = nullptr;
-  int *key = nullptr, *count = nullptr, *start = nullptr, *cursor = nullptr, *tmp = nullptr, *perm = nullptr,
+  int *key = nullptr, *count = nullptr, *start = nullptr, *tmp = nullptr, *perm = nullptr,
       *slot_of = nullptr;
   int *atom_off = nullptr, *form_off = nullptr, *fq_off = nullptr, *site_atoms = nullptr;
   int nbbox = 256;
@@ -152,6 +153,7 @@ mahi_status setup_device(mahi_ctx *ctx, const std::vector<double> &q_env, const 
   HIP_TRY(ctx->alloc(ctx->pot, sizeof(T) * N), "alloc potential");
   HIP_TRY(ctx->alloc(ctx->phi_sorted, sizeof(T) * N), "alloc potential (sorted)");
   HIP_TRY(ctx->alloc(ctx->sorted, sizeof(Atom4<T>) * N), "alloc sorted atoms");
+  HIP_TRY(ctx->alloc(ctx->packed, sizeof(Atom4<T>) * N), "alloc packed atoms");
   // one extra all-zero box row (the source of empty M2L slots); pads stay zero
   HIP_TRY(ctx->alloc(ctx->Mc, sizeof(T) * (nbox + 1) * KS), "alloc multipoles");
   HIP_TRY(ctx->alloc(ctx->Lc, sizeof(T) * (nbox + 1) * KS), "alloc locals");
@@ -164,7 +166,6 @@ mahi_status setup_device(mahi_ctx *ctx, const std::vector<double> &q_env, const 
   HIP_TRY(ctx->alloc(ctx->perm, sizeof(int) * N), "alloc perm");
   HIP_TRY(ctx->alloc(ctx->slot_of, sizeof(int) * N), "alloc slot map");
   HIP_TRY(ctx->alloc(ctx->count, sizeof(int) * nleaf), "alloc counts");
-  HIP_TRY(ctx->alloc(ctx->cursor, sizeof(int) * nleaf), "alloc cursors");
   HIP_TRY(ctx->alloc(ctx->start, sizeof(int) * (nleaf + 1)), "alloc starts");
   HIP_TRY(ctx->alloc(ctx->qds, sizeof(double) * 5 * nleaf), "alloc moments");
   HIP_TRY(ctx->alloc(ctx->epart, sizeof(double) * p2p_blocks<T>(d)), "alloc energy partials");
@@ -293,8 +294,8 @@ mahi_status eval_impl(mahi_ctx *ctx, const mahi_eval_args *a) {
   T *Mc = static_cast<T *>(ctx->Mc), *Lc = static_cast<T *>(ctx->Lc);
   ctx->mark(0);
   if (!ctx->periodic) launch_bbox<T>(xyz, N, ctx->bbox, ctx->nbbox, ctx->geom, st);
-  TreeBufs<T> tb{ctx->key, ctx->count, ctx->start, ctx->cursor, ctx->tmp, ctx->perm, ctx->slot_of,
-                 static_cast<Atom4<T> *>(ctx->sorted)};
+  TreeBufs<T> tb{ctx->key,     ctx->count,   ctx->start, ctx->tmp, ctx->perm, ctx->slot_of,
+                 static_cast<Atom4<T> *>(ctx->packed), static_cast<Atom4<T> *>(ctx->sorted)};
   launch_tree<T>(xyz, static_cast<const T *>(ctx->qt), N, ctx->geom, d, ctx->periodic, tb, st);
   ctx->mark(1);
   launch_p2m<T>(tb.sorted, ctx->start, nleaf, p, KS, Mc + level_offset(d) * KS, ctx->periodic ? ctx->qds : nullptr,
@@ -454,7 +455,7 @@ mahi_status mahi_create(mahi_ctx **out, const mahi_box *box, int64_t n_atoms, co
   ctx->maxa = maxa;
   ctx->maxf = maxf;
   ctx->lambda_set = (M == 0);
-  if (M > 0 && site_lds_bytes(ctx->p, maxa, maxf) + 24 * 1024 > (size_t)std::min<size_t>(prop.sharedMemPerBlock, 65536)) {
+  if (M > 0 && site_lds_bytes(ctx->p, maxa, maxf, false) + kSiteStaticLds > (size_t)std::min<size_t>(prop.sharedMemPerBlock, 65536)) {
     delete ctx;
     return bad(MAHI_ERANGE, "order too high for the site correction's local memory with these site sizes");
   }

@@ -272,19 +272,28 @@ __device__ __forceinline__ void locate(const T *xyz, int64_t i, const Geom &g, i
   }
 }
 
-// Leaf key of every atom and its arrival rank within the leaf (the order of
-// equal keys is fixed later by k_leafsort).
+// Leaf key of every atom, its arrival rank within the leaf (the order of
+// equal keys is fixed later by k_leafsort) and its packed leaf-local
+// coordinates (leaf units, centred) with the scaled charge.
 template <class T>
-__global__ void k_bin(const T *__restrict__ xyz, int64_t n_atoms, const Geom *__restrict__ gp, int d, int periodic,
-                      int *__restrict__ key, int *__restrict__ rank, int *__restrict__ count) {
+__global__ void k_bin(const T *__restrict__ xyz, const T *__restrict__ qt, int64_t n_atoms,
+                      const Geom *__restrict__ gp, int d, int periodic, int *__restrict__ key, int *__restrict__ rank,
+                      int *__restrict__ count, Atom4<T> *__restrict__ packed) {
   const Geom g = *gp;
   const int n = 1 << d;
+  const double inv_h = n / g.edge;
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n_atoms; i += (int64_t)gridDim.x * blockDim.x) {
     double w[3];
     int c[3];
     locate(xyz, i, g, periodic, n, w, c);
     const int k = (int)morton(c[0], c[1], c[2]);
     key[i] = k;
+    Atom4<T> at;
+    at.x = (T)(w[0] * inv_h - (c[0] + 0.5));
+    at.y = (T)(w[1] * inv_h - (c[1] + 0.5));
+    at.z = (T)(w[2] * inv_h - (c[2] + 0.5));
+    at.q = qt[i];
+    packed[i] = at;
     rank[i] = atomicAdd(&count[k], 1);
   }
 }
@@ -348,20 +357,14 @@ __global__ void k_scatter(const int *__restrict__ key, const int *__restrict__ r
 }
 
 // One wave per leaf: order the leaf's atoms by original index (deterministic
-// layout), then write the permutation, its inverse and the packed leaf-local
-// coordinates with scaled charges.
+// layout), then write the permutation, its inverse and the packed atoms.
 template <class T>
 __global__ void __launch_bounds__(256) k_leafsort(const int *__restrict__ tmp, const int *__restrict__ start, int nleaf,
-                                                  const T *__restrict__ xyz, const T *__restrict__ qt,
-                                                  const Geom *__restrict__ gp, int d, int periodic,
-                                                  int *__restrict__ perm, int *__restrict__ slot_of,
-                                                  Atom4<T> *__restrict__ sorted) {
+                                                  const Atom4<T> *__restrict__ packed, int *__restrict__ perm,
+                                                  int *__restrict__ slot_of, Atom4<T> *__restrict__ sorted) {
   const int leaf = blockIdx.x * 4 + (threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
   if (leaf >= nleaf) return;
-  const Geom g = *gp;
-  const int n = 1 << d;
-  const double inv_h = n / g.edge;
   const int s0 = start[leaf], cnt = start[leaf + 1] - s0;
   for (int a = lane; a < cnt; a += 64) {
     const int me = tmp[s0 + a];
@@ -375,15 +378,7 @@ __global__ void __launch_bounds__(256) k_leafsort(const int *__restrict__ tmp, c
     const int slot = s0 + rank;
     perm[slot] = me;
     slot_of[me] = slot;
-    double w[3];
-    int c[3];
-    locate(xyz, me, g, periodic, n, w, c);
-    Atom4<T> at;
-    at.x = (T)(w[0] * inv_h - (c[0] + 0.5));
-    at.y = (T)(w[1] * inv_h - (c[1] + 0.5));
-    at.z = (T)(w[2] * inv_h - (c[2] + 0.5));
-    at.q = qt[me];
-    sorted[slot] = at;
+    sorted[slot] = packed[me];
   }
 }
 
@@ -1296,22 +1291,27 @@ __global__ void k_charge_scale(const int *__restrict__ atom_off, const int *__re
 //   dE_s  = 1/2 (sum_r lt_r q^r.U^r - qt.Ut)               (HI minus charge-scaled intra-site energy)
 //   dF_i  = sum_r lt_r q^r_i W^r_i - qt_i Wt_i,  W = sum_j G_ij q_j, G = -grad_i Phi
 // ---------------------------------------------------------------------------
-template <class T>
-__global__ void __launch_bounds__(64) k_site(SiteArgs a, const T *__restrict__ xyz, const int *__restrict__ slot_of,
-                                             const T *__restrict__ phi_sorted, const Geom *__restrict__ gp,
-                                             const double *__restrict__ LamT, T *__restrict__ F,
-                                             double *__restrict__ dvdl, double *__restrict__ dE_site) {
+template <class T, int PT>
+__global__ void __launch_bounds__(256) k_site(SiteArgs a, const T *__restrict__ xyz, const int *__restrict__ slot_of,
+                                              const T *__restrict__ phi_sorted, const Geom *__restrict__ gp,
+                                              const double *__restrict__ LamT, T *__restrict__ F,
+                                              double *__restrict__ dvdl, double *__restrict__ dE_site) {
+  constexpr int NT = 256;
   extern __shared__ double sm[];
   const int s = blockIdx.x, tid = threadIdx.x;
   const int na = a.atom_off[s + 1] - a.atom_off[s], nf = a.form_off[s + 1] - a.form_off[s];
-  const int K = a.K, p = a.p;
+  const int K = a.K, p = PT > 0 ? PT : a.p;
   __shared__ double x[kMaxSiteAtoms][3], V[kMaxSiteAtoms], qt[kMaxSiteAtoms], ut[kMaxSiteAtoms], lam[kMaxSiteForms];
   __shared__ double qf[kMaxSiteForms][kMaxSiteAtoms];
   __shared__ double U[kMaxSiteForms][kMaxSiteAtoms], W[kMaxSiteForms][kMaxSiteAtoms][3];
-  // dynamic: Rt[maxa][K] (unconjugated Rt at (x - c)/L), om[maxf][K] (site multipoles), Lat[maxf][K] (lattice locals)
-  double *Rt = sm;
-  double *om = Rt + a.maxa * K;
-  double *Lat = om + a.maxf * K;
+  // dynamic: PG[maxa][maxa][4] (pair kernel Phi and G), Rt[maxa][K] (unconjugated Rt at
+  // (x - c)/L), om[maxf][K] (site multipoles), Lat[maxf][LS] (lattice locals, followed by their
+  // gradient coefficients Dx, Dy, Dz when a.dloc: LS = 4K, else LS = K)
+  const int LS = a.dloc ? 4 * K : K;
+  double *PG = sm;
+  double *Rt = PG + (size_t)4 * a.maxa * a.maxa;
+  double *om = Rt + (size_t)a.maxa * K;
+  double *Lat = om + (size_t)a.maxf * K;
 
   const Geom g = *gp;
   const double L = g.edge;
@@ -1324,7 +1324,7 @@ __global__ void __launch_bounds__(64) k_site(SiteArgs a, const T *__restrict__ x
     V[tid] = (double)phi_sorted[slot_of[atom]];
   }
   if (tid < nf) lam[tid] = a.lam[a.form_off[s] + tid];
-  for (int e = tid; e < nf * na; e += 64) {
+  for (int e = tid; e < nf * na; e += NT) {
     const int r = e / na, i = e % na;
     qf[r][i] = a.fq[a.fq_off[s] + r * na + i];
   }
@@ -1334,38 +1334,49 @@ __global__ void __launch_bounds__(64) k_site(SiteArgs a, const T *__restrict__ x
     for (int r = 0; r < nf; ++r) v += lam[r] * qf[r][tid];
     qt[tid] = v;
   }
-  // direct part over the 27 nearest images (+ r^2 part when periodic), contracted with each form
+  // pair kernel over the 27 nearest images (+ r^2 part when periodic), once per atom pair:
+  // PG[i][j] = (Phi_ij, G_ij) with G = -grad_i Phi
   const double c_r2 = a.periodic ? 2.0 * 3.14159265358979323846 / (3.0 * L * L * L) : 0.0;
   const int R = a.periodic ? 1 : 0;
-  for (int e = tid; e < nf * na; e += 64) {
+  for (int e = tid; e < na * na; e += NT) {
+    const int i = e / na, j = e % na;
+    const double rx = x[i][0] - x[j][0], ry = x[i][1] - x[j][1], rz = x[i][2] - x[j][2];
+    double ph = 0.0, gx = 0.0, gy = 0.0, gz = 0.0;
+    for (int ia = -R; ia <= R; ++ia)
+      for (int ib = -R; ib <= R; ++ib)
+        for (int ic = -R; ic <= R; ++ic) {
+          if (i == j && ia == 0 && ib == 0 && ic == 0) continue;
+          const double dx = rx + ia * L, dy = ry + ib * L, dz = rz + ic * L;
+          const double ri = 1.0 / sqrt(dx * dx + dy * dy + dz * dz);
+          ph += ri;
+          const double f = ri * ri * ri;
+          gx += f * dx;
+          gy += f * dy;
+          gz += f * dz;
+        }
+    if (a.periodic) {
+      ph += c_r2 * (rx * rx + ry * ry + rz * rz);
+      gx -= 2.0 * c_r2 * rx;
+      gy -= 2.0 * c_r2 * ry;
+      gz -= 2.0 * c_r2 * rz;
+    }
+    double *pg = PG + (size_t)e * 4;
+    pg[0] = ph;
+    pg[1] = gx;
+    pg[2] = gy;
+    pg[3] = gz;
+  }
+  __syncthreads();
+  for (int e = tid; e < nf * na; e += NT) {
     const int r = e / na, i = e % na;
     double u = 0.0, w0 = 0.0, w1 = 0.0, w2 = 0.0;
     for (int j = 0; j < na; ++j) {
-      const double rx = x[i][0] - x[j][0], ry = x[i][1] - x[j][1], rz = x[i][2] - x[j][2];
-      double ph = 0.0, gx = 0.0, gy = 0.0, gz = 0.0;
-      for (int ia = -R; ia <= R; ++ia)
-        for (int ib = -R; ib <= R; ++ib)
-          for (int ic = -R; ic <= R; ++ic) {
-            if (i == j && ia == 0 && ib == 0 && ic == 0) continue;
-            const double dx = rx + ia * L, dy = ry + ib * L, dz = rz + ic * L;
-            const double ri = 1.0 / sqrt(dx * dx + dy * dy + dz * dz);
-            ph += ri;
-            const double f = ri * ri * ri;
-            gx += f * dx;
-            gy += f * dy;
-            gz += f * dz;
-          }
-      if (a.periodic) {
-        ph += c_r2 * (rx * rx + ry * ry + rz * rz);
-        gx -= 2.0 * c_r2 * rx;
-        gy -= 2.0 * c_r2 * ry;
-        gz -= 2.0 * c_r2 * rz;
-      }
+      const double *pg = PG + (size_t)(i * na + j) * 4;
       const double qj = qf[r][j];
-      u += ph * qj;
-      w0 += gx * qj;
-      w1 += gy * qj;
-      w2 += gz * qj;
+      u += pg[0] * qj;
+      w0 += pg[1] * qj;
+      w1 += pg[2] * qj;
+      w2 += pg[3] * qj;
     }
     U[r][i] = u;
     W[r][i][0] = w0;
@@ -1377,18 +1388,19 @@ __global__ void __launch_bounds__(64) k_site(SiteArgs a, const T *__restrict__ x
     const double half = 0.5 * L, invL = 1.0 / L;
     if (tid < na) {
       double *row = Rt + tid * K;
-      for_regular(p, (x[tid][0] - half) * invL, (x[tid][1] - half) * invL, (x[tid][2] - half) * invL,
-                  [&](int n, int m, double re, double im) {
-                    const int i0 = ridx_d(n, m, 0);
-                    row[i0] = re;
-                    if (m) row[i0 + 1] = im;
-                  });
+      visit_regular<PT>(p, (x[tid][0] - half) * invL, (x[tid][1] - half) * invL, (x[tid][2] - half) * invL,
+                        [&](int n, int m, double re, double im) {
+                          const int i0 = ridx_d(n, m, 0);
+                          row[i0] = re;
+                          if (m) row[i0 + 1] = im;
+                        });
     }
     __syncthreads();
-    for (int e = tid; e < nf * K; e += 64) {
+    for (int e = tid; e < nf * K; e += NT) {
       const int r = e / K, k = e % K;
       // multipole = sum q conj(Rt): the imaginary slots (even, nonzero offset within a degree) flip sign
-      const int nd = (int)floor(sqrt((double)k) + 1e-9);
+      int nd = 0;
+      while ((nd + 1) * (nd + 1) <= k) ++nd;
       const int o = k - nd * nd;
       const double sgn = (o > 0 && (o & 1) == 0) ? -1.0 : 1.0;
       double v = 0.0;
@@ -1396,17 +1408,44 @@ __global__ void __launch_bounds__(64) k_site(SiteArgs a, const T *__restrict__ x
       om[r * K + k] = sgn * v;
     }
     __syncthreads();
-    for (int e = tid; e < nf * K; e += 64) {
+    for (int e = tid; e < nf * K; e += NT) {
       const int r = e / K, k = e % K;
+      const double *orr = om + r * K;
       double v = 0.0;
-      for (int c = 0; c < K; ++c) v += LamT[(int64_t)c * K + k] * om[r * K + c];
-      Lat[r * K + k] = v;
+      int c = 0;
+      for (; c + 8 <= K; c += 8) {
+        double l8[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) l8[u] = LamT[(int64_t)(c + u) * K + k];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) v += l8[u] * orr[c + u];
+      }
+      for (; c < K; ++c) v += LamT[(int64_t)c * K + k] * orr[c];
+      Lat[(size_t)r * LS + k] = v;
     }
     __syncthreads();
-    for (int e = tid; e < nf * na; e += 64) {
+    // gradient coefficients of each form's lattice local (degrees < p)
+    const int nd = a.dloc ? p * p : 0;
+    for (int e = tid; e < nf * nd; e += NT) {
+      const int r = e / nd, k = e % nd;
+      int j = 0;
+      while ((j + 1) * (j + 1) <= k) ++j;
+      const int o = k - j * j;
+      const int b = (o + 1) >> 1;
+      const bool imag = o > 0 && (o & 1) == 0;
+      double xr, xi, yr, yi, zr, zi;
+      double *Lr = Lat + (size_t)r * LS;
+      grad_coeffs(Lr, j, b, xr, xi, yr, yi, zr, zi);
+      Lr[K + k] = imag ? xi : xr;
+      Lr[2 * K + k] = imag ? yi : yr;
+      Lr[3 * K + k] = imag ? zi : zr;
+    }
+    __syncthreads();
+    for (int e = tid; e < nf * na; e += NT) {
       const int r = e / na, i = e % na;
       const double *Rr = Rt + i * K;
-      const double *Lr = Lat + r * K;
+      const double *Lr = Lat + (size_t)r * LS;
+      const double *Dx = Lr + K, *Dy = Dx + K, *Dz = Dy + K;
       double pot = 0.0, gx = 0.0, gy = 0.0, gz = 0.0;
       for (int n = 0; n <= p; ++n)
         for (int m = 0; m <= n; ++m) {
@@ -1416,7 +1455,12 @@ __global__ void __launch_bounds__(64) k_site(SiteArgs a, const T *__restrict__ x
           pot += w * (Lr[i0] * rre + (m ? Lr[i0 + 1] * rim : 0.0));
           if (n < p) {
             double xr, xi, yr, yi, zr, zi;
-            grad_coeffs(Lr, n, m, xr, xi, yr, yi, zr, zi);
+            if (a.dloc) {
+              xr = Dx[i0], yr = Dy[i0], zr = Dz[i0];
+              xi = m ? Dx[i0 + 1] : 0.0, yi = m ? Dy[i0 + 1] : 0.0, zi = m ? Dz[i0 + 1] : 0.0;
+            } else {
+              grad_coeffs(Lr, n, m, xr, xi, yr, yi, zr, zi);
+            }
             gx += w * (xr * rre + xi * rim);
             gy += w * (yr * rre + yi * rim);
             gz += w * (zr * rre + zi * rim);
@@ -1527,12 +1571,12 @@ void launch_tree(const T *xyz, const T *qt, int64_t n, const Geom *g, int d, int
   const int nleaf = 1 << (3 * d);
   // slot_of holds the in-leaf arrival ranks until k_leafsort writes the slots
   launch_fill_i32(b.count, 0, nleaf, st);
-  hipLaunchKernelGGL(k_bin<T>, dim3(grid_for(n, 256)), dim3(256), 0, st, xyz, n, g, d, periodic, b.key, b.slot_of,
-                     b.count);
+  hipLaunchKernelGGL(k_bin<T>, dim3(grid_for(n, 256)), dim3(256), 0, st, xyz, qt, n, g, d, periodic, b.key, b.slot_of,
+                     b.count, b.packed);
   hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, st, b.count, b.start, nleaf);
   hipLaunchKernelGGL(k_scatter, dim3(grid_for(n, 256)), dim3(256), 0, st, b.key, b.slot_of, b.start, b.tmp, n);
-  hipLaunchKernelGGL(k_leafsort<T>, dim3((nleaf + 3) / 4), dim3(256), 0, st, b.tmp, b.start, nleaf, xyz, qt, g, d,
-                     periodic, b.perm, b.slot_of, b.sorted);
+  hipLaunchKernelGGL(k_leafsort<T>, dim3((nleaf + 3) / 4), dim3(256), 0, st, b.tmp, b.start, nleaf, b.packed, b.perm,
+                     b.slot_of, b.sorted);
 }
 
 template <class T>
@@ -1824,18 +1868,27 @@ void launch_charge_scale(const SiteArgs &s, const double *lam, T *qt, hipStream_
                      s.fq_off, lam, s.n_sites, qt);
 }
 
-size_t site_lds_bytes(int p, int maxa, int maxf) {
+// dynamic LDS of k_site: pair kernel, Rt, multipoles and lattice locals (with_d: plus the
+// lattice locals' gradient coefficients)
+size_t site_lds_bytes(int p, int maxa, int maxf, bool with_d) {
   const int K = (p + 1) * (p + 1);
-  return sizeof(double) * ((size_t)maxa * K + 2 * (size_t)maxf * K);
+  return sizeof(double) * (4 * (size_t)maxa * maxa + (size_t)maxa * K + (with_d ? 5 : 2) * (size_t)maxf * K);
 }
 
 template <class T>
 void launch_site(const SiteArgs &s, const T *xyz, const int *slot_of, const T *phi_sorted, const Geom *g,
                  const double *LamT, T *F, double *dvdl, double *dE_site, hipStream_t st) {
   if (s.n_sites == 0) return;
-  const size_t lds = site_lds_bytes(s.p, s.maxa, s.maxf);
-  hipLaunchKernelGGL(k_site<T>, dim3(s.n_sites), dim3(64), lds, st, s, xyz, slot_of, phi_sorted, g, LamT, F, dvdl,
-                     dE_site);
+  SiteArgs a = s;
+  // gradient coefficients in LDS when they fit next to the kernel's static arrays
+  a.dloc = site_lds_bytes(s.p, s.maxa, s.maxf, true) + kSiteStaticLds <= 65536 ? 1 : 0;
+  const size_t lds = site_lds_bytes(s.p, s.maxa, s.maxf, a.dloc != 0);
+  if (s.p == 8)
+    hipLaunchKernelGGL((k_site<T, 8>), dim3(s.n_sites), dim3(256), lds, st, a, xyz, slot_of, phi_sorted, g, LamT, F,
+                       dvdl, dE_site);
+  else
+    hipLaunchKernelGGL((k_site<T, 0>), dim3(s.n_sites), dim3(256), lds, st, a, xyz, slot_of, phi_sorted, g, LamT, F,
+                       dvdl, dE_site);
 }
 
 void launch_finalize(const double *epart, int nb, const double *dE_site, int ns, double ke, double *E, hipStream_t st) {

@@ -31,8 +31,11 @@ struct P2PArgs {
   double ke;
 };
 
+// static LDS of the site kernel (per-site atom, form and result arrays), bytes
+constexpr size_t kSiteStaticLds = 24576;
+
 struct SiteArgs {
-  int n_sites, p, K, periodic, maxa, maxf;
+  int n_sites, p, K, periodic, maxa, maxf, dloc;
   double ke;
   const int *atom_off;    // [M+1] offsets into site_atoms
   const int *form_off;    // [M+1] offsets into the flat form list
@@ -44,8 +47,9 @@ struct SiteArgs {
 
 template <class T>
 struct TreeBufs {
-  int *key, *count, *start, *cursor, *tmp, *perm, *slot_of;
-  Atom4<T> *sorted;
+  int *key, *count, *start, *tmp, *perm, *slot_of;
+  Atom4<T> *packed;  // leaf-local coordinates and scaled charge, input order
+  Atom4<T> *sorted;  // the same, leaf order
 };
 
 hipError_t upload_constants();
@@ -82,6 +86,6 @@ template <class T>
 void launch_site(const SiteArgs &s, const T *xyz, const int *slot_of, const T *phi_sorted, const Geom *g,
                  const double *LamT, T *F, double *dvdl, double *dE_site, hipStream_t st);
 void launch_finalize(const double *epart, int nb, const double *dE_site, int ns, double ke, double *E, hipStream_t st);
-size_t site_lds_bytes(int p, int maxa, int maxf);
+size_t site_lds_bytes(int p, int maxa, int maxf, bool with_d);
 
 }  // namespace mahi
