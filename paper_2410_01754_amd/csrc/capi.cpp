@@ -60,11 +60,20 @@ struct mahi_ctx {
       *slot_of = nullptr;
   int *atom_off = nullptr, *form_off = nullptr, *fq_off = nullptr, *site_atoms = nullptr;
   int nbbox = 256;
-  // stage profiling: events[eval][stage boundary]
+  // second stream (default priority) for the periodic lattice, which needs only
+  // the root multipole and the leaf moments and runs beside M2L; fork/join events
+  hipStream_t side = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+  // stage profiling: events[eval][slot]; slots 0..MAHI_N_STAGES are the stage
+  // boundaries on the main stream, the last two bracket the lattice on the side stream
+  static constexpr int kSlots = MAHI_N_STAGES + 3;
   std::vector<hipEvent_t> prof_events;
   int prof_max = 0, prof_n = 0;
   void mark(int boundary) {
-    if (prof_n < prof_max) (void)hipEventRecord(prof_events[(size_t)prof_n * (MAHI_N_STAGES + 1) + boundary], stream);
+    if (prof_n < prof_max) (void)hipEventRecord(prof_events[(size_t)prof_n * kSlots + boundary], stream);
+  }
+  void mark_side(int which) {
+    if (prof_n < prof_max) (void)hipEventRecord(prof_events[(size_t)prof_n * kSlots + MAHI_N_STAGES + 1 + which], side);
   }
 
   mahi_status fail(mahi_status s, const std::string &m) {
@@ -172,6 +181,9 @@ mahi_status setup_device(mahi_ctx *ctx, const std::vector<double> &q_env, const 
   HIP_TRY(ctx->alloc(ctx->E, sizeof(double) * 1), "alloc energy");
   HIP_TRY(ctx->alloc(ctx->bbox, sizeof(double) * 6 * ctx->nbbox), "alloc bbox");
   HIP_TRY(ctx->alloc(ctx->geom, sizeof(Geom)), "alloc geometry");
+  HIP_TRY(hipStreamCreateWithFlags(&ctx->side, hipStreamNonBlocking), "side stream");
+  HIP_TRY(hipEventCreateWithFlags(&ctx->ev_fork, hipEventDisableTiming), "event create");
+  HIP_TRY(hipEventCreateWithFlags(&ctx->ev_join, hipEventDisableTiming), "event create");
   Geom g{};
   g.edge = ctx->periodic ? ctx->edge : 1.0;
   HIP_TRY(hipMemcpy(ctx->geom, &g, sizeof(Geom), hipMemcpyHostToDevice), "upload geometry");
@@ -305,7 +317,16 @@ mahi_status eval_impl(mahi_ctx *ctx, const mahi_eval_args *a) {
   const int mlow = ctx->periodic ? 0 : 2;
   for (int l = d - 1; l >= mlow; --l) launch_updown<T>(Mc, static_cast<const T *>(ctx->m2m), p, KS, l, true, st);
   ctx->mark(3);
-  if (ctx->periodic) launch_lattice<T>(Mc, Lc, ctx->LamT, ncoef(p), ctx->qds, nleaf, ctx->geom, st);
+  if (ctx->periodic) {
+    // the lattice (root local L_0 and the moments Q, D, S2) on the side stream, beside M2L,
+    // which writes only levels >= 1; joined before L2L reads L_0
+    HIP_TRY(hipEventRecord(ctx->ev_fork, st), "fork");
+    HIP_TRY(hipStreamWaitEvent(ctx->side, ctx->ev_fork, 0), "fork");
+    ctx->mark_side(0);
+    launch_lattice<T>(Mc, Lc, ctx->LamT, ncoef(p), ctx->qds, nleaf, ctx->geom, ctx->side);
+    ctx->mark_side(1);
+    HIP_TRY(hipEventRecord(ctx->ev_join, ctx->side), "join");
+  }
   ctx->mark(4);
   if (d >= lmin) {
     if constexpr (sizeof(T) == sizeof(float))
@@ -315,6 +336,7 @@ mahi_status eval_impl(mahi_ctx *ctx, const mahi_eval_args *a) {
       launch_xlate_m2l<T>(Mc, Lc, static_cast<const T *>(ctx->m2l), ctx->lists, p, KS, d, ctx->periodic, st);
   }
   ctx->mark(5);
+  if (ctx->periodic) HIP_TRY(hipStreamWaitEvent(st, ctx->ev_join, 0), "join");
   for (int l = ctx->periodic ? 1 : 3; l <= d; ++l)
     launch_updown<T>(Lc, static_cast<const T *>(ctx->l2l), p, KS, l - 1, false, st);
   ctx->mark(6);
@@ -347,8 +369,12 @@ void free_ctx(mahi_ctx *ctx) {
   if (!ctx) return;
   (void)hipSetDevice(ctx->device);
   if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
+  if (ctx->side) (void)hipStreamSynchronize(ctx->side);
   for (auto &e : ctx->prof_events) (void)hipEventDestroy(e);
   for (auto &b : ctx->bufs) (void)hipFree(b.p);
+  if (ctx->ev_fork) (void)hipEventDestroy(ctx->ev_fork);
+  if (ctx->ev_join) (void)hipEventDestroy(ctx->ev_join);
+  if (ctx->side) (void)hipStreamDestroy(ctx->side);
   if (ctx->own_stream && ctx->stream) (void)hipStreamDestroy(ctx->stream);
   delete ctx;
 }
@@ -548,7 +574,7 @@ mahi_status mahi_profile_begin(mahi_ctx *ctx, int max_evals) {
   HIP_TRY(hipSetDevice(ctx->device), "set device");
   HIP_TRY(hipStreamSynchronize(ctx->stream), "synchronise");
   for (auto &e : ctx->prof_events) (void)hipEventDestroy(e);
-  ctx->prof_events.assign((size_t)max_evals * (MAHI_N_STAGES + 1), nullptr);
+  ctx->prof_events.assign((size_t)max_evals * mahi_ctx::kSlots, nullptr);
   for (auto &e : ctx->prof_events) HIP_TRY(hipEventCreate(&e), "event create");
   ctx->prof_max = max_evals;
   ctx->prof_n = 0;
@@ -560,12 +586,16 @@ mahi_status mahi_profile_end(mahi_ctx *ctx, double *stage_ms, int *n_evals) {
   HIP_TRY(hipSetDevice(ctx->device), "set device");
   HIP_TRY(hipStreamSynchronize(ctx->stream), "synchronise");
   for (int s = 0; s < MAHI_N_STAGES; ++s) stage_ms[s] = 0.0;
+  HIP_TRY(hipStreamSynchronize(ctx->side), "synchronise");
   for (int e = 0; e < ctx->prof_n; ++e)
     for (int s = 0; s < MAHI_N_STAGES; ++s) {
+      // stage s between main-stream boundaries s and s + 1, except the lattice (periodic),
+      // which runs on the side stream between its own two events
+      const size_t base = (size_t)e * mahi_ctx::kSlots;
+      const bool side = s == 3 && ctx->periodic;
+      const size_t a0 = side ? base + MAHI_N_STAGES + 1 : base + s;
       float ms = 0.f;
-      HIP_TRY(hipEventElapsedTime(&ms, ctx->prof_events[(size_t)e * (MAHI_N_STAGES + 1) + s],
-                                  ctx->prof_events[(size_t)e * (MAHI_N_STAGES + 1) + s + 1]),
-              "event timing");
+      HIP_TRY(hipEventElapsedTime(&ms, ctx->prof_events[a0], ctx->prof_events[a0 + 1]), "event timing");
       stage_ms[s] += ms;
     }
   if (ctx->prof_n > 0)
