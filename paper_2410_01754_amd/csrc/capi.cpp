@@ -60,12 +60,13 @@ struct mahi_ctx {
       *slot_of = nullptr;
   int *atom_off = nullptr, *form_off = nullptr, *fq_off = nullptr, *site_atoms = nullptr;
   int nbbox = 256;
-  // second stream (default priority) for the periodic lattice, which needs only
-  // the root multipole and the leaf moments and runs beside M2L; fork/join events
+  // second stream (default priority) for the upper tree levels (M2M above the two
+  // deepest levels, the periodic lattice, their M2L and L2L), beside the main
+  // M2L; fork/join events
   hipStream_t side = nullptr;
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   // stage profiling: events[eval][slot]; slots 0..MAHI_N_STAGES are the stage
-  // boundaries on the main stream, the last two bracket the lattice on the side stream
+  // boundaries on the main stream, the last two bracket the upper levels on the side stream
   static constexpr int kSlots = MAHI_N_STAGES + 3;
   std::vector<hipEvent_t> prof_events;
   int prof_max = 0, prof_n = 0;
@@ -313,32 +314,40 @@ mahi_status eval_impl(mahi_ctx *ctx, const mahi_eval_args *a) {
   launch_p2m<T>(tb.sorted, ctx->start, nleaf, p, KS, Mc + level_offset(d) * KS, ctx->periodic ? ctx->qds : nullptr,
                 ctx->geom, d, st);
   ctx->mark(2);
+  // Levels hl..d (hl = max(lmin, d - 1)) carry almost all M2L work.  After the
+  // whole upward pass the side stream takes M2L of levels lmin..hl-1 (issued
+  // first, so its blocks are dispatched beside the main launch), the periodic
+  // lattice and L2L into levels up to hl - 1, while the main stream runs M2L of
+  // levels hl..d.  The two write disjoint level ranges; the main stream joins
+  // before L2L into levels hl..d.
   const int lmin = ctx->periodic ? 1 : 2;
   const int mlow = ctx->periodic ? 0 : 2;
-  for (int l = d - 1; l >= mlow; --l) launch_updown<T>(Mc, static_cast<const T *>(ctx->m2m), p, KS, l, true, st);
-  ctx->mark(3);
-  if (ctx->periodic) {
-    // the lattice (root local L_0 and the moments Q, D, S2) on the side stream, beside M2L,
-    // which writes only levels >= 1; joined before L2L reads L_0
-    HIP_TRY(hipEventRecord(ctx->ev_fork, st), "fork");
-    HIP_TRY(hipStreamWaitEvent(ctx->side, ctx->ev_fork, 0), "fork");
-    ctx->mark_side(0);
-    launch_lattice<T>(Mc, Lc, ctx->LamT, ncoef(p), ctx->qds, nleaf, ctx->geom, ctx->side);
-    ctx->mark_side(1);
-    HIP_TRY(hipEventRecord(ctx->ev_join, ctx->side), "join");
-  }
-  ctx->mark(4);
-  if (d >= lmin) {
+  const int l2l_first = ctx->periodic ? 1 : 3;
+  const int hl = std::max(lmin, d - 1);
+  const T *Tm2m = static_cast<const T *>(ctx->m2m), *Tl2l = static_cast<const T *>(ctx->l2l);
+  auto m2l = [&](int lo, int hi, hipStream_t s) {
+    if (d < lmin || lo > hi) return;
     if constexpr (sizeof(T) == sizeof(float))
       launch_m2l_f32(Mc, Lc, static_cast<float *>(ctx->part), static_cast<const float *>(ctx->m2l), ctx->lists,
-                     ctx->plan32, st);
+                     ctx->plan32, lo, hi, s);
     else
-      launch_xlate_m2l<T>(Mc, Lc, static_cast<const T *>(ctx->m2l), ctx->lists, p, KS, d, ctx->periodic, st);
-  }
+      launch_xlate_m2l<T>(Mc, Lc, static_cast<const T *>(ctx->m2l), ctx->lists, p, KS, d, ctx->periodic, lo, hi, s);
+  };
+  for (int l = d - 1; l >= mlow; --l) launch_updown<T>(Mc, Tm2m, p, KS, l, true, st);
+  ctx->mark(3);
+  HIP_TRY(hipEventRecord(ctx->ev_fork, st), "fork");
+  HIP_TRY(hipStreamWaitEvent(ctx->side, ctx->ev_fork, 0), "fork");
+  ctx->mark_side(0);
+  m2l(lmin, hl - 1, ctx->side);
+  if (ctx->periodic) launch_lattice<T>(Mc, Lc, ctx->LamT, ncoef(p), ctx->qds, nleaf, ctx->geom, ctx->side);
+  for (int l = l2l_first; l <= std::min(hl - 1, d); ++l) launch_updown<T>(Lc, Tl2l, p, KS, l - 1, false, ctx->side);
+  ctx->mark_side(1);
+  HIP_TRY(hipEventRecord(ctx->ev_join, ctx->side), "join");
+  ctx->mark(4);
+  m2l(hl, d, st);
   ctx->mark(5);
-  if (ctx->periodic) HIP_TRY(hipStreamWaitEvent(st, ctx->ev_join, 0), "join");
-  for (int l = ctx->periodic ? 1 : 3; l <= d; ++l)
-    launch_updown<T>(Lc, static_cast<const T *>(ctx->l2l), p, KS, l - 1, false, st);
+  HIP_TRY(hipStreamWaitEvent(st, ctx->ev_join, 0), "join");
+  for (int l = std::max(hl, l2l_first); l <= d; ++l) launch_updown<T>(Lc, Tl2l, p, KS, l - 1, false, st);
   ctx->mark(6);
   launch_p2p<T>(tb.sorted, ctx->start, ctx->perm, Lc + level_offset(d) * KS, KS, ctx->geom, d, ctx->periodic, p, ctx->ke,
                 static_cast<T *>(ctx->phi_sorted), F, pot, ctx->epart, st);
@@ -564,7 +573,7 @@ mahi_status mahi_info(const mahi_ctx *ctx, int64_t *n_atoms, int32_t *n_sites, i
 }
 
 const char *mahi_stage_name(int stage) {
-  static const char *names[MAHI_N_STAGES] = {"tree", "p2m", "m2m", "lattice", "m2l", "l2l", "p2p_l2p", "site", "energy"};
+  static const char *names[MAHI_N_STAGES] = {"tree", "p2m", "m2m", "upper_levels", "m2l", "l2l", "p2p_l2p", "site", "energy"};
   return (stage >= 0 && stage < MAHI_N_STAGES) ? names[stage] : "unknown";
 }
 
@@ -589,10 +598,10 @@ mahi_status mahi_profile_end(mahi_ctx *ctx, double *stage_ms, int *n_evals) {
   HIP_TRY(hipStreamSynchronize(ctx->side), "synchronise");
   for (int e = 0; e < ctx->prof_n; ++e)
     for (int s = 0; s < MAHI_N_STAGES; ++s) {
-      // stage s between main-stream boundaries s and s + 1, except the lattice (periodic),
-      // which runs on the side stream between its own two events
+      // stage s between main-stream boundaries s and s + 1, except stage 3 (the
+      // upper levels), which runs on the side stream between its own two events
       const size_t base = (size_t)e * mahi_ctx::kSlots;
-      const bool side = s == 3 && ctx->periodic;
+      const bool side = s == 3;
       const size_t a0 = side ? base + MAHI_N_STAGES + 1 : base + s;
       float ms = 0.f;
       HIP_TRY(hipEventElapsedTime(&ms, ctx->prof_events[a0], ctx->prof_events[a0 + 1]), "event timing");

@@ -744,11 +744,11 @@ k_m2l_f32(const float *__restrict__ M, float *__restrict__ Out, const float *__r
   __shared__ float As[2][KC * RG];
 
   // ---- work item (blocks of one XCD take consecutive items)
-  const int nitems = a.nsplit * a.ngroups * a.ntiles;
+  const int nitems = a.nsplit * a.ngroups * a.tile_run;
   const int bid = blockIdx.x;
   const int item = (bid & 7) * (nitems >> 3) + (bid >> 3);
-  const int tile = item % a.ntiles;
-  const int rest = item / a.ntiles;
+  const int tile = a.tile0 + item % a.tile_run;
+  const int rest = item / a.tile_run;
   const int grp = rest % a.ngroups;
   const int split = rest / a.ngroups;
   int l = a.lmin;
@@ -906,11 +906,11 @@ k_m2l16_f32(const float *__restrict__ M, float *__restrict__ Out, const float *_
   __shared__ float As[2][AFL];
 
   // ---- work item (blocks of one XCD take consecutive items)
-  const int nitems = a.nsplit * a.ngroups * a.ntiles;
+  const int nitems = a.nsplit * a.ngroups * a.tile_run;
   const int bid = blockIdx.x;
   const int item = (bid & 7) * (nitems >> 3) + (bid >> 3);
-  const int tile = item % a.ntiles;
-  const int split = item / a.ntiles;
+  const int tile = a.tile0 + item % a.tile_run;
+  const int split = item / a.tile_run;
   int l = a.lmin;
   while (l < a.d && tile >= a.tiles_start[l + 1]) ++l;
   const int tl = tile - a.tiles_start[l];
@@ -1820,25 +1820,25 @@ static void xlate_launch(const XArgs &a, int blocks, hipStream_t st, Args... arg
 
 
 template <class T>
-void launch_xlate_m2l(const T *M, T *L, const T *Tab, const int4 *lists, int p, int KS, int d, int periodic,
-                      hipStream_t st) {
+void launch_xlate_m2l(const T *M, T *L, const T *Tab, const int4 *lists, int p, int KS, int d, int periodic, int lev_lo,
+                      int lev_hi, hipStream_t st) {
   XArgs a;
   xlate_geometry<T>(p, a);
   a.KS = KS;
-  a.d = d;
+  a.d = std::min(d, lev_hi);
   a.periodic = periodic;
-  a.lmin = periodic ? 1 : 2;
+  a.lmin = std::max(periodic ? 1 : 2, lev_lo);
   a.nops = kListLen;
   a.level = 0;
   int blocks = 0;
   for (int l = 0; l <= 8; ++l) a.level_start[l] = 0;
-  for (int l = a.lmin; l <= d; ++l) {
+  for (int l = a.lmin; l <= a.d; ++l) {
     a.level_start[l] = blocks;
     const int64_t np = int64_t(1) << (3 * (l - 1));
     blocks += (int)(8 * ((np + 63) / 64) * a.ngroups);
   }
-  if (d + 1 <= 8) a.level_start[d + 1] = blocks;
-  if (blocks == 0) return;
+  if (a.d + 1 <= 8) a.level_start[a.d + 1] = blocks;
+  if (a.lmin > a.d || blocks == 0) return;
   xlate_launch<T, XL_M2L>(a, blocks, st, M, L, Tab, lists);
 }
 
@@ -1899,6 +1899,8 @@ void m2l32_plan(int p, int d, int periodic, int n_cu, M2LPlan &a) {
     a.ntiles += (int)(8 * ((ntg + kM2LTile - 1) / kM2LTile));
   }
   if (d + 1 <= 8) a.tiles_start[d + 1] = a.ntiles;
+  a.tile0 = 0;
+  a.tile_run = a.ntiles;
   // operator ranges: the split count minimising a fluid makespan model with
   // two resident blocks per CU, in units of one operator step of a block:
   //   max(work / slots + item / 2, item) + overhead * splits,
@@ -1921,17 +1923,23 @@ void m2l32_plan(int p, int d, int periodic, int n_cu, M2LPlan &a) {
   }
 }
 
-void launch_m2l_f32(const float *M, float *L, float *part, const float *Tab, const int4 *lists, const M2LPlan &a,
-                    hipStream_t st) {
-  if (a.ntiles == 0) return;
-  const int blocks = a.nsplit * a.ngroups * a.ntiles;
+void launch_m2l_f32(const float *M, float *L, float *part, const float *Tab, const int4 *lists, const M2LPlan &plan,
+                    int lev_lo, int lev_hi, hipStream_t st) {
+  lev_lo = std::max(lev_lo, plan.lmin);
+  lev_hi = std::min(lev_hi, plan.d);
+  if (plan.ntiles == 0 || lev_lo > lev_hi) return;
+  M2LPlan a = plan;
+  a.tile0 = plan.tiles_start[lev_lo];
+  a.tile_run = plan.tiles_start[lev_hi + 1] - a.tile0;  // a multiple of 8 (8 classes per chunk)
+  if (a.tile_run <= 0) return;
+  const int blocks = a.nsplit * a.ngroups * a.tile_run;
   float *out = a.nsplit > 1 ? part : L;
   if (a.ns == 21)
     hipLaunchKernelGGL(k_m2l16_f32, dim3(blocks), dim3(256), 0, st, M, out, Tab, lists, a);
   else
     hipLaunchKernelGGL(k_m2l_f32<40>, dim3(blocks), dim3(256), 0, st, M, out, Tab, lists, a);
   if (a.nsplit > 1) {
-    const int64_t b0 = level_offset(a.lmin), b1 = level_offset(a.d + 1);
+    const int64_t b0 = level_offset(lev_lo), b1 = level_offset(lev_hi + 1);
     const int64_t v0 = b0 * a.KS / 4, v1 = b1 * a.KS / 4;
     const int64_t n = v1 - v0;
     const int grid = (int)std::min<int64_t>((n + 255) / 256, 4096);
@@ -2103,7 +2111,8 @@ void launch_finalize(const double *epart, int nb, const double *dE_site, int ns,
   template void launch_lattice<T>(const T *, T *, const double *, int, const double *, int, Geom *, hipStream_t);    \
   template void m2l_table_layout<T>(int, int &, int &);                                                               \
   template void launch_mfma_probe<T>(const T *, const T *, T *, int, int, hipStream_t);                              \
-  template void launch_xlate_m2l<T>(const T *, T *, const T *, const int4 *, int, int, int, int, hipStream_t);         \
+  template void launch_xlate_m2l<T>(const T *, T *, const T *, const int4 *, int, int, int, int, int, int,            \
+                                    hipStream_t);                                                                   \
   template void launch_xlate_m2m<T>(T *, int, const T *, const int4 *, int, int, hipStream_t);                        \
   template void launch_xlate_l2l<T>(T *, int, const T *, const int4 *, int, int, hipStream_t);                        \
   template void updown_table<T>(int, int, const double *const *, T *);                                               \

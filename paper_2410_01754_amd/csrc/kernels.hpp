@@ -15,6 +15,7 @@ constexpr int kM2LMaxSplit = 8;
 
 struct M2LPlan {
   int K, KS, ns, nkc, ngroups, nsplit, ntiles;
+  int tile0, tile_run;  // tiles of one launch (a level range)
   int d, lmin, periodic;
   int64_t nbox, zbox;  // boxes over all levels; index of the all-zero multipole row
   int tiles_start[9];
@@ -64,13 +65,13 @@ template <class T>
 void launch_lattice(const T *M, T *L, const double *LamT, int K, const double *qds, int nleaf, Geom *g, hipStream_t st);
 template <class T> void m2l_table_layout(int p, int &KK, int &RP);
 template <class T>
-void launch_xlate_m2l(const T *M, T *L, const T *Tab, const int4 *lists, int p, int KS, int d, int periodic,
-                      hipStream_t st);
+void launch_xlate_m2l(const T *M, T *L, const T *Tab, const int4 *lists, int p, int KS, int d, int periodic, int lev_lo,
+                      int lev_hi, hipStream_t st);
 template <class T> void launch_xlate_m2m(T *M, int lp, const T *Tab, const int4 *ops, int p, int KS, hipStream_t st);
 template <class T> void launch_xlate_l2l(T *L, int lc, const T *Tab, const int4 *ops, int p, int KS, hipStream_t st);
 void m2l32_plan(int p, int d, int periodic, int n_cu, M2LPlan &a);
-void launch_m2l_f32(const float *M, float *L, float *part, const float *Tab, const int4 *lists, const M2LPlan &a,
-                    hipStream_t st);
+void launch_m2l_f32(const float *M, float *L, float *part, const float *Tab, const int4 *lists, const M2LPlan &plan,
+                    int lev_lo, int lev_hi, hipStream_t st);
 void m2l32_table(const M2LPlan &a, int slot, const double *Tv, float *dst);
 size_t m2l32_table_size(const M2LPlan &a, int nslots);
 template <class T> void updown_table(int K, int KS, const double *const *Tc, T *A);
