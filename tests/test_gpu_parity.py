@@ -74,6 +74,20 @@ def test_open_depth0_float64_reproduces_oracle():
 
 
 @pytest.mark.parametrize("prec", [64, 32])
+def test_open_depth4_p8(prec):
+    """Open boundaries at depth 4: M2L of levels 2..3 and L2L into level 3 run on the
+    library's second stream beside M2L of levels 4..5 (here 4)."""
+    s = make_system(1000, 3.1, False, [6, 8, 5, 7], [2, 3, 2, 4], qrange=(-0.9, 0.9), total_step=None,
+                    clustered=True, simplex=True, depth=4, seed=41, name="open3.1")
+    E, F, dv, _ = oracle(s)
+    g = gpu_eval(s, prec, 8, 4)
+    print("open d4 p8", prec, abs(g["energy"] - E) / abs(E), rel(g["forces"], F), rel(g["dvdl"], dv))
+    assert abs(g["energy"] - E) <= 2e-4 * abs(E)
+    assert rel(g["forces"], F) <= 2e-4
+    assert rel(g["dvdl"], dv) <= 2e-4
+
+
+@pytest.mark.parametrize("prec", [64, 32])
 def test_open_config0_depth2_p8(prec):
     s = make_config(0)
     E, F, dv, _ = oracle(s)
