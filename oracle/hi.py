@@ -65,11 +65,13 @@ def hi_dense(q, sites, Phi, G, ke=KE_DEFAULT):
     return ke * E, ke * F, ke * np.array(dvdl), dedq
 
 
-def hi_periodic(x, q, sites, L, ke=KE_DEFAULT, targets=None, nthreads=0, alpha=None):
+def hi_periodic(x, q, sites, L, ke=KE_DEFAULT, targets=None, nthreads=0, alpha=None, qi=False):
     """HI outputs for a periodic cube via Ewald sums.
 
     Returns E, F, dvdl, dedq.  With `targets` given, F is returned only for
     those atoms and E is None (the energy needs the potential at every atom).
+    With qi=True two more values follow, the charge-interpolation outputs of
+    qi_dense from the same field: E_QI (None with `targets`) and dvdl_QI.
     """
     x = np.asarray(x, dtype=np.float64)
     n = x.shape[0]
@@ -109,9 +111,33 @@ def hi_periodic(x, q, sites, L, ke=KE_DEFAULT, targets=None, nthreads=0, alpha=N
             dq[r] = st.lam[r] * (Vext[ia] + Pss @ qr)
         dedq.append(ke * dq)
     Eo = None if E is None else ke * E
-    if targets is None:
-        return Eo, ke * F, ke * np.array(dvdl), dedq
-    return Eo, (tg, ke * F), ke * np.array(dvdl), dedq
+    out = (Eo, ke * F, ke * np.array(dvdl), dedq) if targets is None else (Eo, (tg, ke * F), ke * np.array(dvdl), dedq)
+    if not qi:
+        return out
+    # phi is the full scaled-charge potential (before the site blocks were removed)
+    dv_qi = [st.charges[r] @ phi[ia] for st, (ia, _, _) in zip(sites, blocks) for r in range(st.charges.shape[0])]
+    E_qi = ke * 0.5 * qt[tg] @ phi if targets is None else None
+    return out + (E_qi, ke * np.array(dv_qi))
+
+
+def qi_dense(q, sites, Phi, ke=KE_DEFAULT):
+    """Charge interpolation (section "Comparison of Hamiltonian and Charge
+    Interpolation"): the scaled charges treated as fixed charges,
+      E_QI = 1/2 qt.Phi.qt,   dE_QI/dlt_srho = sum_{i in s} q^rho_i (Phi qt)_i
+    (chain rule through qt_i = sum_rho lt_rho q^rho_i).  Returns E_QI, dvdl_QI."""
+    qt, _ = scaled_charges(Phi.shape[0], q, sites)
+    V = Phi @ qt
+    dv = [st.charges[r] @ V[st.atoms] for st in sites for r in range(st.charges.shape[0])]
+    return ke * 0.5 * qt @ V, ke * np.array(dv)
+
+
+def qi_periodic(x, q, sites, L, ke=KE_DEFAULT, nthreads=0, alpha=None):
+    """qi_dense for a periodic cube: Phi qt from the Ewald field at every atom."""
+    x = np.asarray(x, dtype=np.float64)
+    qt, _ = scaled_charges(x.shape[0], q, sites)
+    V, _ = ewald.field(x, qt, L, alpha=alpha, nthreads=nthreads)
+    dv = [st.charges[r] @ V[st.atoms] for st in sites for r in range(st.charges.shape[0])]
+    return ke * 0.5 * qt @ V, ke * np.array(dv)
 
 
 def evaluate(system, ke=KE_DEFAULT, dense_limit=3000, nthreads=0):

@@ -2,9 +2,11 @@
 
 Calls only oracle/ and synth/ (never the GPU library).  Output per config:
 tests/golden/config<k>_oracle.npz with the HI energy, dE/dlambda-tilde of
-every form, and forces at every site atom plus a seeded sample of other atoms.
+every form, dE/dq of every form charge, the charge-interpolation energy and
+its dE/dlambda-tilde, and forces at every site atom plus a seeded sample of
+other atoms.
 
-Usage: python tests/golden/make_golden.py 1 [2]
+Usage: [ORACLE_THREADS=n] python tests/golden/make_golden.py 1 [2]
 """
 import os
 import sys
@@ -31,12 +33,15 @@ def sample_atoms(system, n_env=4000, seed=99):
 def main(k):
     s = make_config(k)
     t = time.time()
-    E, F, dvdl, dedq = hi.hi_periodic(s.x, s.q, s.sites, s.box)
-    dt = time.time() - t
     idx = sample_atoms(s)
+    nthreads = int(os.environ.get("ORACLE_THREADS", "0"))  # 0: every host core
+    E, F, dvdl, dedq, E_qi, dvdl_qi = hi.hi_periodic(s.x, s.q, s.sites, s.box, qi=True, nthreads=nthreads)
+    dt = time.time() - t
     out = os.path.join(HERE, f"config{k}_oracle.npz")
     np.savez_compressed(out, energy=np.array([E]), dvdl=dvdl, idx=idx, forces=F[idx],
-                        force_norm=np.array([np.linalg.norm(F)]), seconds=np.array([dt]))
+                        force_norm=np.array([np.linalg.norm(F)]), seconds=np.array([dt]),
+                        dedq=np.concatenate([d.reshape(-1) for d in dedq]), energy_qi=np.array([E_qi]),
+                        dvdl_qi=dvdl_qi)
     print(f"config{k}: N={s.n_atoms} E={E:.10f} oracle {dt:.1f}s -> {out}", flush=True)
 
 

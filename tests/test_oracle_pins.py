@@ -82,13 +82,60 @@ def test_single_two_form_site_closed_form(periodic):
     for lam in (0.0, 0.345, 0.721, 1.0):
         s = base.with_lam([1 - lam, lam])
         E, _, dvdl, _ = hi.hi_dense(s.q, s.sites, Phi, G)
-        qt, _ = hi.scaled_charges(s.n_atoms, s.q, s.sites)
-        E_qi = 0.5 * KE * qt @ Phi @ qt
+        E_qi, dv_qi = hi.qi_dense(s.q, s.sites, Phi)
         assert abs((E_qi - E) - KE * 0.5 * k * (lam * lam - lam)) <= 1e-10 * abs(E)
         dH = dvdl[1] - dvdl[0]
-        dqt = st.charges[1] - st.charges[0]
-        dQI = KE * dqt @ (Phi @ qt)[st.atoms]
+        dQI = dv_qi[1] - dv_qi[0]
         assert abs((dQI - dH) - KE * (lam - 0.5) * k) <= 1e-9 * max(abs(dH), 1.0)
+
+
+def test_qi_dropped_cross_term_is_caught(monkeypatch):
+    """Planted mistake: a QI energy without the site-environment cross term breaks the closed form."""
+    base = make_system(20, 1.4, False, [5], [2], total_step=1.0, depth=0, seed=11)
+    Phi, G = dense(base)
+    st = base.sites[0]
+    d = st.charges[0] - st.charges[1]
+    k = d @ Phi[np.ix_(st.atoms, st.atoms)] @ d
+    s = base.with_lam([0.655, 0.345])
+    E, _, _, _ = hi.hi_dense(s.q, s.sites, Phi, G)
+    qt, site_of = hi.scaled_charges(s.n_atoms, s.q, s.sites)
+    cut = np.where((site_of[:, None] >= 0) != (site_of[None, :] >= 0), 0.0, Phi)
+    monkeypatch.setattr(hi, "qi_dense", lambda q, sites, P, ke=KE: (ke * 0.5 * qt @ cut @ qt, None))
+    E_qi, _ = hi.qi_dense(s.q, s.sites, Phi)
+    assert abs((E_qi - E) - KE * 0.5 * k * (0.345 ** 2 - 0.345)) > 1e-6 * abs(E)
+
+
+def test_qi_outputs_of_hi_periodic_match_dense():
+    s = small(True, seed=10)
+    Phi, _ = dense(s)
+    Ed, dvd = hi.qi_dense(s.q, s.sites, Phi)
+    out = hi.hi_periodic(s.x, s.q, s.sites, s.box, qi=True)
+    assert abs(out[4] - Ed) <= 1e-11 * abs(Ed) and rel(out[5], dvd) <= 1e-11
+    part = hi.hi_periodic(s.x, s.q, s.sites, s.box, targets=[0, 1], qi=True)
+    assert part[4] is None and rel(part[5], dvd) <= 1e-11
+
+
+def test_qi_periodic_derivative_by_central_difference():
+    """dE_QI/dlt from qi_periodic equals the central difference of its E_QI (E_QI is
+    quadratic in the weights, so the difference is exact up to rounding), and the
+    Ewald-field path agrees with the dense pair-kernel path."""
+    s = small(True, seed=9)
+    E0, dv = hi.qi_periodic(s.x, s.q, s.sites, s.box)
+    Phi, _ = dense(s)
+    Ed, dvd = hi.qi_dense(s.q, s.sites, Phi)
+    assert abs(E0 - Ed) <= 1e-11 * abs(Ed) and rel(dv, dvd) <= 1e-11
+    lam = s.lam_flat()
+    h = 1e-3
+    k = 0
+    for si, st in enumerate(s.sites):
+        for r in range(st.charges.shape[0]):
+            lp, lm = lam.copy(), lam.copy()
+            lp[k] += h
+            lm[k] -= h
+            Ep, _ = hi.qi_periodic(s.x, s.q, s.with_lam(lp).sites, s.box)
+            Em, _ = hi.qi_periodic(s.x, s.q, s.with_lam(lm).sites, s.box)
+            assert abs((Ep - Em) / (2 * h) - dv[k]) <= 1e-7 * max(abs(dv[k]), 1.0)
+            k += 1
 
 
 # ---------------------------------------------------------------- P4: vertices
