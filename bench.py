@@ -11,6 +11,7 @@ Reported next to the headline ns/eval:
   * the plain FMM on the same scaled charges with no sites (MAHI overhead %),
   * per-stage mean durations from HIP events recorded on the library's stream
     over the timed region, and the roofline of the dominant kernel (M2L),
+  * the site correction alone (mahi_correct) on a given potential,
   * the CPU oracle on a bounded sample (same recipe, smaller cube), scaled to
     the full system by the oracle's measured size exponent.
 
@@ -57,22 +58,22 @@ def p2p_pairs(system, depth: int) -> int:
     return int((cnt * nb).sum() - system.n_atoms)
 
 
-KERNELS_SRC = os.path.join(ROOT, "paper_2410_01754_amd", "csrc", "kernels.hip")
+M2L_SRC = os.path.join(ROOT, "paper_2410_01754_amd", "csrc", "m2l_f32.hip")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "m2l_traffic.txt")
 
 
 def m2l_traffic():
     """HBM bytes per M2L launch from the committed FETCH_SIZE / WRITE_SIZE counter
-    runs (scaled by the copy-kernel calibration), or None when the kernel source
-    has changed since they were taken."""
+    runs (scaled by the copy-kernel calibration), or None when the source file
+    of the float32 M2L kernel has changed since they were taken."""
     try:
         with open(TRAFFIC_FILE) as f:
             rec = json.load(f)
-        with open(KERNELS_SRC, "rb") as f:
+        with open(M2L_SRC, "rb") as f:
             sha = hashlib.sha256(f.read()).hexdigest()
     except (OSError, ValueError):
         return None
-    if rec.get("kernels_sha256") != sha:
+    if rec.get("source_sha256") != sha:
         return None
     return float(rec["bytes_per_launch"])
 
@@ -152,6 +153,20 @@ def main():
     x32 = torch.from_numpy(s.x).to(dev)
     o32 = outputs(torch.float32, s.n_forms)
     t32, stages = time_evals(m32, x32, o32, args.steps, args.warmup, profile=True)
+    # the site correction alone on a potential from another solver (here the
+    # tree's own, written by one evaluation)
+    pot = torch.zeros(s.n_atoms, dtype=torch.float32, device=dev)
+    m32.eval_device(x32.data_ptr(), o32["E"].data_ptr(), o32["F"].data_ptr(), o32["dvdl"].data_ptr(),
+                    pot.data_ptr())
+    ec = torch.zeros(1, dtype=torch.float64, device=dev)
+    for _ in range(3):
+        m32.correct_device(x32.data_ptr(), pot.data_ptr(), ec.data_ptr(), o32["F"].data_ptr(), o32["dvdl"].data_ptr())
+    torch.cuda.synchronize()
+    tc0 = time.perf_counter()
+    for _ in range(args.steps):
+        m32.correct_device(x32.data_ptr(), pot.data_ptr(), ec.data_ptr(), o32["F"].data_ptr(), o32["dvdl"].data_ptr())
+    torch.cuda.synchronize()
+    tcorr = (time.perf_counter() - tc0) / args.steps
     # one evaluator at a time: each holds a second stream, which helps only with a
     # hardware queue of its own
     m32.close()
@@ -188,6 +203,7 @@ def main():
         "fp64_ns_per_eval": t64 * 1e9,
         "fp32_speedup_over_fp64": t64 / t32,
         "plain_fmm_ns_per_eval": tplain * 1e9,
+        "correction_only_ns_per_call": tcorr * 1e9,
         "mahi_overhead_pct": 100.0 * (t32 / tplain - 1.0),
         "m2l_translations": trans,
         "m2l_translations_all_levels": m2l_translations(s.depth, True),

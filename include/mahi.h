@@ -103,6 +103,17 @@ typedef struct {
                          potential of the charge-scaled Hamiltonian, including
                          the atom's own periodic images), same type as xyz; may be NULL */
   uint32_t flags;     /* 0 or MAHI_DEVICE_IO */
+  /* Derivatives for fitting and for charge interpolation (all may be NULL):  */
+  double *dedq;       /* [sum forms * atoms] dE/dq^(s,r)_i for every form charge, in the
+                         layout of mahi_sites.form_charges.  Every weight and form
+                         charge is an independent variable of the general
+                         formulation (eq iter_ham_lambda):
+                         dE/dq^(s,r)_i = coulomb_k lt_r (V_i + sum_{j in s} Phi_ij (q^(s,r)_j - qt_j)) */
+  double *energy_qi;  /* [1] charge-interpolated (QI) energy coulomb_k/2 qt.Phi.qt: the
+                         energy of the scaled charges alone, before the site
+                         correction (section "Differences Between Hamiltonian and
+                         Charge Interpolation") */
+  double *dvdl_qi;    /* [sum forms] dE_QI/dlambda-tilde = coulomb_k sum_{i in s} q^(s,r)_i V_i */
 } mahi_eval_args;
 
 /* Create a context: validates everything, chooses no parameters on its own,
@@ -127,6 +138,52 @@ mahi_status mahi_set_lambda(mahi_ctx *ctx, const double *lambda_tilde);
  * Without MAHI_DEVICE_IO the call copies host inputs and outputs and waits
  * for the GPU.                                                              */
 mahi_status mahi_eval(mahi_ctx *ctx, const mahi_eval_args *args);
+
+/* Replace the charges of every form of every site (same layout and checks as
+ * mahi_sites.form_charges at creation; the site atoms and form counts stay).
+ * The scaled charges are formed again from the current lambda-tilde (when
+ * one has been set).  For fitting form charges with dedq.  Non-finite values
+ * give MAHI_EINVAL and leave the context unchanged.                        */
+mahi_status mahi_set_form_charges(mahi_ctx *ctx, const double *form_charges);
+
+/* Solver-agnostic site correction (paper, section "GROMACS performance with
+ * FMM and constant pH": the corrections act on a charge-scaled potential V computed by
+ * any method that is accurate enough, e.g. particle-mesh Ewald).  Given V at
+ * every atom from another solver, this runs only the per-site correction of
+ * mahi_eval (eqs correction_scheme to C_B) on the context's sites:
+ *   E_HI  = E_QI + *energy,   F_HI = F_QI + (the correction added to forces),
+ *   dvdl, dedq as in mahi_eval (they need V at the site atoms only).
+ * The site kernel is the one mahi_eval uses: periodic pairs take the 27
+ * nearest images plus the lattice remainder of order `order` (with the r^2
+ * term of a tin-foil, neutralised cell), i.e. the Ewald pair potential.
+ * No octree work is done; the context's depth is irrelevant here.           */
+typedef struct {
+  const void *xyz;        /* [N][3] positions (nm), type as mahi_eval; only site atoms are read */
+  const void *potential;  /* [N] coulomb_k * V_i (the charge-scaled potential at each atom,
+                             including the atom's own periodic images, in the form of
+                             mahi_eval's potential output); only site atoms are read */
+  double *energy;         /* [1] E_HI - E_QI; may be NULL */
+  void *forces;           /* [N][3] F_HI - F_QI is ADDED at site atoms (other entries are
+                             not touched); may be NULL */
+  double *dvdl;           /* [sum forms] dE_HI/dlambda-tilde; may be NULL */
+  double *dedq;           /* [sum forms * atoms] dE_HI/dq^(s,r)_i; may be NULL */
+  uint32_t flags;         /* 0 or MAHI_DEVICE_IO */
+} mahi_correct_args;
+mahi_status mahi_correct(mahi_ctx *ctx, const mahi_correct_args *args);
+
+/* Binary multi-form sites (paper, appendix: eqs lambda_list and
+ * one_site_lambda and the mapping of derivatives that follows them; section
+ * "Calculation of Forces on lambda Particles").  A site with 2^L forms is
+ * driven by L original lambdas; form r gets
+ *   lt_r = prod_k (lambda_k if bit k of r is set, else 1 - lambda_k)
+ * (least significant bit = lambda_0), and
+ *   dE/dlambda_k = sum_r s(r,k) f(r,k) dE/dlt_r
+ * with s = +1 when bit k of r is set, -1 otherwise, and f the product of the
+ * other L-1 factors of lt_r.  Host only; n_lambda in 1..4 (2..16 forms);
+ * MAHI_EINVAL for NULL pointers or non-finite values.                       */
+mahi_status mahi_lambda_tilde(int n_lambda, const double *lambda, double *lambda_tilde /* [2^n_lambda] */);
+mahi_status mahi_dlambda(int n_lambda, const double *lambda, const double *dvdl /* [2^n_lambda] */,
+                         double *dlambda /* [n_lambda] */);
 
 /* Release every host and device resource of the context (NULL is allowed). */
 void mahi_destroy(mahi_ctx *ctx);

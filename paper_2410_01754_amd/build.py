@@ -24,7 +24,7 @@ def build(verbose: bool = False) -> str:
     objs = []
     bdir = os.path.join(HERE, "_build")
     os.makedirs(bdir, exist_ok=True)
-    for src, dev in (("kernels.hip", True), ("capi.cpp", True), ("tables.cpp", False)):
+    for src, dev in (("kernels.hip", True), ("m2l_f32.hip", True), ("capi.cpp", True), ("tables.cpp", False)):
         obj = os.path.join(bdir, src + ".o")
         cmd = [HIPCC] + COMMON + (DEVICE_FLAGS if dev else ["-x", "c++"]) + ["-c", os.path.join(CSRC, src), "-o", obj]
         if dev and src.endswith(".cpp"):

@@ -43,6 +43,7 @@ struct mahi_ctx {
   bool own_stream = false;
   int device = 0;
   int M = 0, nforms = 0, nsite_atoms = 0, maxa = 0, maxf = 0;
+  int64_t nfq = 0;  // form charges over all sites
   bool lambda_set = false;
   std::string err;
   std::vector<DevBuf> bufs;
@@ -54,6 +55,7 @@ struct mahi_ctx {
   void *Mc = nullptr, *Lc = nullptr, *m2l = nullptr, *m2m = nullptr, *l2l = nullptr, *sorted = nullptr;
   double *LamT = nullptr, *qds = nullptr, *epart = nullptr, *dE_site = nullptr, *dvdl = nullptr, *E = nullptr;
   double *bbox = nullptr, *lam = nullptr, *fq = nullptr;
+  double *dedq = nullptr, *dvdl_qi = nullptr, *E_qi = nullptr;  // host-I/O staging of the optional outputs
   int4 *lists = nullptr;
   Geom *geom = nullptr;
   int *key = nullptr, *count = nullptr, *start = nullptr, *tmp = nullptr, *perm = nullptr,
@@ -180,6 +182,7 @@ mahi_status setup_device(mahi_ctx *ctx, const std::vector<double> &q_env, const 
   HIP_TRY(ctx->alloc(ctx->qds, sizeof(double) * 5 * nleaf), "alloc moments");
   HIP_TRY(ctx->alloc(ctx->epart, sizeof(double) * p2p_blocks<T>(d)), "alloc energy partials");
   HIP_TRY(ctx->alloc(ctx->E, sizeof(double) * 1), "alloc energy");
+  HIP_TRY(ctx->alloc(ctx->E_qi, sizeof(double) * 1), "alloc energy");
   HIP_TRY(ctx->alloc(ctx->bbox, sizeof(double) * 6 * ctx->nbbox), "alloc bbox");
   HIP_TRY(ctx->alloc(ctx->geom, sizeof(Geom)), "alloc geometry");
   HIP_TRY(hipStreamCreateWithFlags(&ctx->side, hipStreamNonBlocking), "side stream");
@@ -256,6 +259,8 @@ mahi_status setup_device(mahi_ctx *ctx, const std::vector<double> &q_env, const 
     HIP_TRY(ctx->alloc(ctx->fq, sizeof(double) * fq.size()), "alloc sites");
     HIP_TRY(ctx->alloc(ctx->lam, sizeof(double) * ctx->nforms), "alloc lambda");
     HIP_TRY(ctx->alloc(ctx->dvdl, sizeof(double) * ctx->nforms), "alloc dvdl");
+    HIP_TRY(ctx->alloc(ctx->dvdl_qi, sizeof(double) * ctx->nforms), "alloc dvdl");
+    HIP_TRY(ctx->alloc(ctx->dedq, sizeof(double) * fq.size()), "alloc dE/dq");
     HIP_TRY(ctx->alloc(ctx->dE_site, sizeof(double) * ctx->M), "alloc site energies");
     HIP_TRY(hipMemcpy(ctx->atom_off, atom_off.data(), sizeof(int) * atom_off.size(), hipMemcpyHostToDevice), "upload");
     HIP_TRY(hipMemcpy(ctx->form_off, form_off.data(), sizeof(int) * form_off.size(), hipMemcpyHostToDevice), "upload");
@@ -303,6 +308,9 @@ mahi_status eval_impl(mahi_ctx *ctx, const mahi_eval_args *a) {
   double *E = (dev && a->energy) ? a->energy : ctx->E;
   double *dvdl = (dev && a->dvdl) ? a->dvdl : ctx->dvdl;
   if (ctx->M > 0 && !dvdl) dvdl = ctx->dvdl;
+  double *dedq = (ctx->M > 0 && a->dedq) ? (dev ? a->dedq : ctx->dedq) : nullptr;
+  double *dvdl_qi = (ctx->M > 0 && a->dvdl_qi) ? (dev ? a->dvdl_qi : ctx->dvdl_qi) : nullptr;
+  double *E_qi = a->energy_qi ? (dev ? a->energy_qi : ctx->E_qi) : nullptr;
 
   T *Mc = static_cast<T *>(ctx->Mc), *Lc = static_cast<T *>(ctx->Lc);
   ctx->mark(0);
@@ -354,11 +362,11 @@ mahi_status eval_impl(mahi_ctx *ctx, const mahi_eval_args *a) {
   ctx->mark(7);
   if (ctx->M > 0) {
     SiteArgs s = site_args<T>(ctx);
-    launch_site<T>(s, xyz, ctx->slot_of, static_cast<const T *>(ctx->phi_sorted), ctx->geom, ctx->LamT, F, dvdl,
-                   ctx->dE_site, st);
+    const SiteIO<T> io{static_cast<const T *>(ctx->phi_sorted), nullptr, F, dvdl, ctx->dE_site, dedq, dvdl_qi};
+    launch_site<T>(s, xyz, ctx->slot_of, ctx->geom, ctx->LamT, io, st);
   }
   ctx->mark(8);
-  launch_finalize(ctx->epart, p2p_blocks<T>(d), ctx->dE_site, ctx->M, ctx->ke, E, st);
+  launch_finalize(ctx->epart, p2p_blocks<T>(d), ctx->dE_site, ctx->M, ctx->ke, E, E_qi, st);
   ctx->mark(9);
   if (ctx->prof_n < ctx->prof_max) ++ctx->prof_n;
   HIP_TRY(hipGetLastError(), "kernel launch");
@@ -369,9 +377,65 @@ mahi_status eval_impl(mahi_ctx *ctx, const mahi_eval_args *a) {
     if (a->forces) HIP_TRY(hipMemcpyAsync(a->forces, ctx->F, sizeof(T) * 3 * N, hipMemcpyDeviceToHost, st), "copy forces");
     if (a->potential)
       HIP_TRY(hipMemcpyAsync(a->potential, ctx->pot, sizeof(T) * N, hipMemcpyDeviceToHost, st), "copy potential");
+    if (dedq)
+      HIP_TRY(hipMemcpyAsync(a->dedq, dedq, sizeof(double) * ctx->nfq, hipMemcpyDeviceToHost, st), "copy dE/dq");
+    if (dvdl_qi)
+      HIP_TRY(hipMemcpyAsync(a->dvdl_qi, dvdl_qi, sizeof(double) * ctx->nforms, hipMemcpyDeviceToHost, st),
+              "copy dvdl_qi");
+    if (E_qi) HIP_TRY(hipMemcpyAsync(a->energy_qi, E_qi, sizeof(double), hipMemcpyDeviceToHost, st), "copy energy");
     HIP_TRY(hipStreamSynchronize(st), "evaluation");
   }
   return MAHI_OK;
+}
+
+// Site correction on a potential from another solver: k_site reads ke * V from
+// `potential` (user order) instead of the tree's potential; the energy is the
+// sum of the per-site corrections.
+template <class T>
+mahi_status correct_impl(mahi_ctx *ctx, const mahi_correct_args *a) {
+  const bool dev = (a->flags & MAHI_DEVICE_IO) != 0;
+  const int64_t N = ctx->N;
+  hipStream_t st = ctx->stream;
+  HIP_TRY(hipSetDevice(ctx->device), "set device");
+  const T *xyz = static_cast<const T *>(a->xyz), *pot = static_cast<const T *>(a->potential);
+  T *F = static_cast<T *>(a->forces);
+  if (!dev) {
+    HIP_TRY(hipMemcpyAsync(ctx->xyz, a->xyz, sizeof(T) * 3 * N, hipMemcpyHostToDevice, st), "copy positions");
+    HIP_TRY(hipMemcpyAsync(ctx->pot, a->potential, sizeof(T) * N, hipMemcpyHostToDevice, st), "copy potential");
+    xyz = static_cast<const T *>(ctx->xyz);
+    pot = static_cast<const T *>(ctx->pot);
+    if (F) {
+      HIP_TRY(hipMemcpyAsync(ctx->F, a->forces, sizeof(T) * 3 * N, hipMemcpyHostToDevice, st), "copy forces");
+      F = static_cast<T *>(ctx->F);
+    }
+  }
+  double *E = (dev && a->energy) ? a->energy : ctx->E;
+  double *dvdl = a->dvdl ? (dev ? a->dvdl : ctx->dvdl) : nullptr;
+  double *dedq = a->dedq ? (dev ? a->dedq : ctx->dedq) : nullptr;
+  if (ctx->M > 0) {
+    SiteArgs s = site_args<T>(ctx);
+    const SiteIO<T> io{nullptr, pot, F, dvdl, ctx->dE_site, dedq, nullptr};
+    launch_site<T>(s, xyz, ctx->slot_of, ctx->geom, ctx->LamT, io, st);
+  }
+  launch_finalize(nullptr, 0, ctx->dE_site, ctx->M, ctx->ke, E, nullptr, st);
+  HIP_TRY(hipGetLastError(), "kernel launch");
+  if (!dev) {
+    if (a->energy) HIP_TRY(hipMemcpyAsync(a->energy, ctx->E, sizeof(double), hipMemcpyDeviceToHost, st), "copy energy");
+    if (dvdl)
+      HIP_TRY(hipMemcpyAsync(a->dvdl, dvdl, sizeof(double) * ctx->nforms, hipMemcpyDeviceToHost, st), "copy dvdl");
+    if (dedq) HIP_TRY(hipMemcpyAsync(a->dedq, dedq, sizeof(double) * ctx->nfq, hipMemcpyDeviceToHost, st), "copy dE/dq");
+    if (F) HIP_TRY(hipMemcpyAsync(a->forces, F, sizeof(T) * 3 * N, hipMemcpyDeviceToHost, st), "copy forces");
+    HIP_TRY(hipStreamSynchronize(st), "correction");
+  }
+  return MAHI_OK;
+}
+
+template <class T>
+bool all_finite(const void *p, int64_t n) {
+  const T *x = static_cast<const T *>(p);
+  for (int64_t i = 0; i < n; ++i)
+    if (!std::isfinite(x[i])) return false;
+  return true;
 }
 
 void free_ctx(mahi_ctx *ctx) {
@@ -487,6 +551,7 @@ mahi_status mahi_create(mahi_ctx **out, const mahi_box *box, int64_t n_atoms, co
   ctx->M = M;
   ctx->nforms = form_off.back();
   ctx->nsite_atoms = (int)site_atoms.size();
+  ctx->nfq = (int64_t)fq.size();
   ctx->maxa = maxa;
   ctx->maxf = maxf;
   ctx->lambda_set = (M == 0);
@@ -544,18 +609,97 @@ mahi_status mahi_eval(mahi_ctx *ctx, const mahi_eval_args *a) {
   if (a->flags & ~MAHI_DEVICE_IO) return ctx->fail(MAHI_EINVAL, "unknown flags");
   if (!ctx->lambda_set) return ctx->fail(MAHI_ESTATE, "mahi_set_lambda must be called before mahi_eval");
   if (!(a->flags & MAHI_DEVICE_IO)) {
-    const int64_t n3 = 3 * ctx->N;
-    if (ctx->prec == 32) {
-      const float *x = static_cast<const float *>(a->xyz);
-      for (int64_t i = 0; i < n3; ++i)
-        if (!std::isfinite(x[i])) return ctx->fail(MAHI_EINVAL, "non-finite coordinate");
-    } else {
-      const double *x = static_cast<const double *>(a->xyz);
-      for (int64_t i = 0; i < n3; ++i)
-        if (!std::isfinite(x[i])) return ctx->fail(MAHI_EINVAL, "non-finite coordinate");
-    }
+    const bool ok = ctx->prec == 32 ? all_finite<float>(a->xyz, 3 * ctx->N) : all_finite<double>(a->xyz, 3 * ctx->N);
+    if (!ok) return ctx->fail(MAHI_EINVAL, "non-finite coordinate");
   }
   return ctx->prec == 32 ? eval_impl<float>(ctx, a) : eval_impl<double>(ctx, a);
+}
+
+mahi_status mahi_correct(mahi_ctx *ctx, const mahi_correct_args *a) {
+  if (!ctx) return MAHI_EINVAL;
+  if (!a || !a->xyz || !a->potential) return ctx->fail(MAHI_EINVAL, "args, args->xyz and args->potential must not be NULL");
+  if (a->flags & ~MAHI_DEVICE_IO) return ctx->fail(MAHI_EINVAL, "unknown flags");
+  if (!ctx->lambda_set) return ctx->fail(MAHI_ESTATE, "mahi_set_lambda must be called before mahi_correct");
+  if (!(a->flags & MAHI_DEVICE_IO)) {
+    const bool f32 = ctx->prec == 32;
+    if (!(f32 ? all_finite<float>(a->xyz, 3 * ctx->N) : all_finite<double>(a->xyz, 3 * ctx->N)))
+      return ctx->fail(MAHI_EINVAL, "non-finite coordinate");
+    if (!(f32 ? all_finite<float>(a->potential, ctx->N) : all_finite<double>(a->potential, ctx->N)))
+      return ctx->fail(MAHI_EINVAL, "non-finite potential");
+  }
+  return ctx->prec == 32 ? correct_impl<float>(ctx, a) : correct_impl<double>(ctx, a);
+}
+
+mahi_status mahi_set_form_charges(mahi_ctx *ctx, const double *form_charges) {
+  if (!ctx) return MAHI_EINVAL;
+  if (ctx->M == 0) return MAHI_OK;
+  if (!form_charges) return ctx->fail(MAHI_EINVAL, "form_charges is NULL");
+  if (!all_finite<double>(form_charges, ctx->nfq)) return ctx->fail(MAHI_EINVAL, "non-finite form charge");
+  HIP_TRY(hipSetDevice(ctx->device), "set device");
+  HIP_TRY(hipMemcpyAsync(ctx->fq, form_charges, sizeof(double) * ctx->nfq, hipMemcpyHostToDevice, ctx->stream),
+          "copy form charges");
+  if (ctx->lambda_set) {
+    if (ctx->prec == 32)
+      launch_charge_scale<float>(site_args<float>(ctx), ctx->lam, static_cast<float *>(ctx->qt), ctx->stream);
+    else
+      launch_charge_scale<double>(site_args<double>(ctx), ctx->lam, static_cast<double *>(ctx->qt), ctx->stream);
+    HIP_TRY(hipGetLastError(), "charge scaling launch");
+  }
+  HIP_TRY(hipStreamSynchronize(ctx->stream), "form charges");
+  return MAHI_OK;
+}
+
+mahi_status mahi_lambda_tilde(int n_lambda, const double *lambda, double *lt) {
+  if (n_lambda < 1 || n_lambda > 4) return MAHI_ERANGE;
+  if (!lambda || !lt) return MAHI_EINVAL;
+  for (int k = 0; k < n_lambda; ++k)
+    if (!is_fin(lambda[k])) return MAHI_EINVAL;
+  // lt over forms 0..2^k-1 doubles at each k: forms with bit k clear take
+  // (1 - lambda_k), the others lambda_k
+  lt[0] = 1.0;
+  for (int k = 0; k < n_lambda; ++k) {
+    const int h = 1 << k;
+    for (int r = 0; r < h; ++r) {
+      lt[h + r] = lt[r] * lambda[k];
+      lt[r] *= 1.0 - lambda[k];
+    }
+  }
+  return MAHI_OK;
+}
+
+mahi_status mahi_dlambda(int n_lambda, const double *lambda, const double *dvdl, double *dlambda) {
+  if (n_lambda < 1 || n_lambda > 4) return MAHI_ERANGE;
+  if (!lambda || !dvdl || !dlambda) return MAHI_EINVAL;
+  const int nf = 1 << n_lambda;
+  for (int k = 0; k < n_lambda; ++k)
+    if (!is_fin(lambda[k])) return MAHI_EINVAL;
+  for (int r = 0; r < nf; ++r)
+    if (!is_fin(dvdl[r])) return MAHI_EINVAL;
+  for (int k = 0; k < n_lambda; ++k) {
+    // d lt_r / d lambda_k = +-(product of the other factors): the weights of
+    // the remaining n_lambda - 1 lambdas, indexed by r with bit k removed
+    double other[8];
+    int n_other = 0;
+    for (int j = 0; j < n_lambda; ++j)
+      if (j != k) other[n_other++] = lambda[j];
+    double w[8];
+    w[0] = 1.0;
+    for (int j = 0; j < n_other; ++j) {
+      const int h = 1 << j;
+      for (int r = 0; r < h; ++r) {
+        w[h + r] = w[r] * other[j];
+        w[r] *= 1.0 - other[j];
+      }
+    }
+    double acc = 0.0;
+    for (int r = 0; r < nf; ++r) {
+      const int lo = r & ((1 << k) - 1), hi = r >> (k + 1);
+      const double f = w[lo | (hi << k)];
+      acc += ((r >> k) & 1) ? f * dvdl[r] : -f * dvdl[r];
+    }
+    dlambda[k] = acc;
+  }
+  return MAHI_OK;
 }
 
 void mahi_destroy(mahi_ctx *ctx) { free_ctx(ctx); }

@@ -65,4 +65,6 @@ __device__ inline double wrap_coord(double x, double L) {
   return w;
 }
 
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+
 }  // namespace mahi

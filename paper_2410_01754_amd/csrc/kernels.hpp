@@ -46,6 +46,22 @@ struct SiteArgs {
   const double *lam;      // [sum forms]
 };
 
+// Inputs and outputs of the site correction.  The charge-scaled potential at a
+// site atom comes from the tree (phi_sorted, leaf order, without ke) or, when
+// pot_ext is set, from another solver (user order, scaled by ke).  F is
+// accumulated at site atoms; every pointer except one potential may be null
+// (dE_site is required).
+template <class T>
+struct SiteIO {
+  const T *phi_sorted;
+  const T *pot_ext;
+  T *F;
+  double *dvdl;     // [sum forms] ke (sum_i q^r_i V_i - C^r)
+  double *dE_site;  // [M] intra-site correction energy (without ke)
+  double *dedq;     // [sum forms * atoms] dE/dq^(s,r)_i, layout of the form charges
+  double *dvdl_qi;  // [sum forms] ke sum_i q^r_i V_i (charge-interpolated derivative)
+};
+
 template <class T>
 struct TreeBufs {
   int *key, *count, *start, *tmp, *perm, *slot_of;
@@ -84,9 +100,10 @@ void launch_p2p(const Atom4<T> *sorted, const int *start, const int *perm, const
                 int periodic, int p, double ke, T *phi_sorted, T *F, T *pot_user, double *epart, hipStream_t st);
 template <class T> void launch_charge_scale(const SiteArgs &s, const double *lam, T *qt, hipStream_t st);
 template <class T>
-void launch_site(const SiteArgs &s, const T *xyz, const int *slot_of, const T *phi_sorted, const Geom *g,
-                 const double *LamT, T *F, double *dvdl, double *dE_site, hipStream_t st);
-void launch_finalize(const double *epart, int nb, const double *dE_site, int ns, double ke, double *E, hipStream_t st);
+void launch_site(const SiteArgs &s, const T *xyz, const int *slot_of, const Geom *g, const double *LamT,
+                 const SiteIO<T> &io, hipStream_t st);
+void launch_finalize(const double *epart, int nb, const double *dE_site, int ns, double ke, double *E, double *E_qi,
+                     hipStream_t st);
 size_t site_lds_bytes(int p, int maxa, int maxf, bool with_d);
 
 }  // namespace mahi

@@ -1,0 +1,489 @@
+// Float32 M2L on the matrix cores (paper, section "Fast Multipole Method":
+// the multipole-to-local translation of the far field, for every box of
+// levels 1..d (periodic) or 2..d (open) over its 189-box interaction list).
+// Kernels, the work decomposition (M2LPlan) and the operator table layout.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+
+#include "device_common.hpp"
+#include "kernels.hpp"
+
+namespace mahi {
+
+typedef float floatx16 __attribute__((ext_vector_type(16)));
+
+// ---------------------------------------------------------------------------
+// M2L in float32 on the matrix cores, operator shared through LDS.
+// Work item: (level, parity class, 128 consecutive targets of that class, row
+// group of 96 output rows, range of operators of the 189-entry list).  A block
+// has 4 waves; wave w owns 32 targets (one 32-column MFMA tile) and the 3 row
+// tiles of the group.  For every (operator v, k chunk):
+//   * the block stages T_v (96 rows x KC) once in LDS (double buffered);
+//   * each wave holds its 32 gathered source multipoles in registers, loaded
+//     as float4 from the padded multipole rows (stride KS, a multiple of 8);
+//   * each wave runs 3 x NS MFMA 32x32x2 into 3 accumulator tiles.
+// In k-step s the lanes of half h (lane >> 5) contract
+//   k = 8 (s / 4) + 4 h + s % 4
+// (the k index of one MFMA is internal to the instruction, so any pairing of
+// the two halves works as long as A and B agree): each lane's B values are
+// runs of 4 consecutive k, one float4 load per 4 steps.  The operator rows are
+// stored pre-permuted (LDS row 2s + h holds that k); a chunk of NS = 40 steps
+// covers 80 consecutive k.  Used for orders above 8 (k_m2l16_f32 serves the
+// rest).  Several operator ranges of one target tile write separate partial
+// sums that k_m2l_reduce adds in a fixed order.
+// ---------------------------------------------------------------------------
+
+template <int NS>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2)))
+k_m2l_f32(const float *__restrict__ M, float *__restrict__ Out, const float *__restrict__ Tab,
+          const int4 *__restrict__ lists, M2LPlan a) {
+  constexpr int RG = kM2LRowGroup;  // rows per group (3 tiles of 32)
+  constexpr int KC = 2 * NS;        // operator rows (k values) per chunk
+  constexpr int NQ = (NS + 3) / 4;  // float4 loads per lane per chunk
+  constexpr int AV = KC * RG / 4;   // float4 elements of one staged operator chunk
+  constexpr int AR = (AV + 255) / 256;
+  __shared__ float As[2][KC * RG];
+
+  // ---- work item (blocks of one XCD take consecutive items)
+  const int nitems = a.nsplit * a.ngroups * a.tile_run;
+  const int bid = blockIdx.x;
+  const int item = (bid & 7) * (nitems >> 3) + (bid >> 3);
+  const int tile = a.tile0 + item % a.tile_run;
+  const int rest = item / a.tile_run;
+  const int grp = rest % a.ngroups;
+  const int split = rest / a.ngroups;
+  int l = a.lmin;
+  while (l < a.d && tile >= a.tiles_start[l + 1]) ++l;
+  const int tl = tile - a.tiles_start[l];
+  const int cls = tl & 7, chunk = tl >> 3;
+  const int o0 = split * kListLen / a.nsplit, o1 = (split + 1) * kListLen / a.nsplit;
+  const int nit = (o1 - o0) * a.nkc;
+
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int h = lane >> 5, j = lane & 31;
+  const int nl = 1 << l;
+  const int64_t ntg = int64_t(1) << (3 * (l - 1));
+  const int64_t P = (int64_t)chunk * kM2LTile + wave * 32 + j;
+  const bool valid = P < ntg;
+  // waves whose 32 targets are all empty (levels with few boxes) skip the matrix work
+  const bool wave_busy = (int64_t)chunk * kM2LTile + wave * 32 < ntg;
+  int tx = 0, ty = 0, tz = 0;
+  if (valid) unmorton((uint32_t)(8 * P + cls), tx, ty, tz);
+  const int64_t off = level_offset(l);
+  const int4 *lst = lists + cls * kListLen;
+
+  // source row (in boxes) of operator iteration `it`, or the all-zero row
+  auto src_row = [&](int it) -> int64_t {
+    const int4 v = lst[o0 + it / a.nkc];
+    int sx = tx - v.x, sy = ty - v.y, sz = tz - v.z;
+    bool ok = valid;
+    if (a.periodic) {
+      sx = (sx + 4 * nl) & (nl - 1);
+      sy = (sy + 4 * nl) & (nl - 1);
+      sz = (sz + 4 * nl) & (nl - 1);
+    } else {
+      ok = ok && (unsigned)sx < (unsigned)nl && (unsigned)sy < (unsigned)nl && (unsigned)sz < (unsigned)nl;
+    }
+    return ok ? off + (int64_t)morton(sx, sy, sz) : a.zbox;
+  };
+  auto load_b = [&](int it, float *b) {
+    const int c = it % a.nkc;
+    const floatx4 *q = reinterpret_cast<const floatx4 *>(M + src_row(it) * a.KS + c * kM2LKC + 4 * h);
+#pragma unroll
+    for (int i = 0; i < NQ; ++i) {
+      const floatx4 v = q[2 * i];
+#pragma unroll
+      for (int e = 0; e < 4; ++e)
+        if (4 * i + e < NS) b[4 * i + e] = v[e];
+    }
+  };
+  auto a_src = [&](int it) {
+    const int4 v = lst[o0 + it / a.nkc];
+    const int c = it % a.nkc;
+    return reinterpret_cast<const floatx4 *>(Tab + (((int64_t)v.w * a.ngroups + grp) * a.nkc + c) * (KC * RG));
+  };
+  auto load_a = [&](int it, floatx4 *r) {
+    const floatx4 *q = a_src(it);
+#pragma unroll
+    for (int i = 0; i < AR; ++i) {
+      const int e = threadIdx.x + 256 * i;
+      if (e < AV) r[i] = q[e];
+    }
+  };
+  auto store_a = [&](int buf, const floatx4 *r) {
+    floatx4 *dst = reinterpret_cast<floatx4 *>(As[buf]);
+#pragma unroll
+    for (int i = 0; i < AR; ++i) {
+      const int e = threadIdx.x + 256 * i;
+      if (e < AV) dst[e] = r[i];
+    }
+  };
+
+  floatx16 acc[3];
+#pragma unroll
+  for (int t = 0; t < 3; ++t)
+#pragma unroll
+    for (int r = 0; r < 16; ++r) acc[t][r] = 0.f;
+
+  float b0[NS], b1[NS];
+  floatx4 ast[AR];
+  load_a(0, ast);
+  store_a(0, ast);
+  load_a(min(1, nit - 1), ast);
+  load_b(0, b0);
+  __syncthreads();
+
+  // one (operator, chunk) iteration: stage the next operator, prefetch the
+  // next sources, then 3 x NS matrix-core steps on LDS buffer it & 1
+  auto body = [&](int it, const float *bc, float *bn) {
+    const int buf = it & 1;
+    store_a(buf ^ 1, ast);
+    load_a(min(it + 2, nit - 1), ast);
+    load_b(min(it + 1, nit - 1), bn);
+    const float *Ar = As[buf] + h * RG + j;
+    if (wave_busy) {
+#pragma unroll
+      for (int s2 = 0; s2 < NS; ++s2) {
+#pragma unroll
+        for (int t = 0; t < 3; ++t)
+          acc[t] = __builtin_amdgcn_mfma_f32_32x32x2f32(Ar[2 * s2 * RG + 32 * t], bc[s2], acc[t], 0, 0, 0);
+      }
+    }
+    __syncthreads();
+  };
+  for (int it = 0; it < nit; it += 2) {
+    body(it, b0, b1);
+    if (it + 1 < nit) body(it + 1, b1, b0);
+  }
+
+  // ---- results: lane (h, j) holds rows 8q + 4h + {0..3} of each row tile for target j
+  if (!valid) return;
+  const int64_t tb = off + 8 * P + cls;
+  float *dst = Out + ((int64_t)split * a.nbox + tb) * a.KS;
+#pragma unroll
+  for (int t = 0; t < 3; ++t)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int row = grp * RG + 32 * t + 8 * q + 4 * h;
+      if (row < a.KS) {
+        floatx4 v;
+        v[0] = acc[t][4 * q];
+        v[1] = acc[t][4 * q + 1];
+        v[2] = acc[t][4 * q + 2];
+        v[3] = acc[t][4 * q + 3];
+        *reinterpret_cast<floatx4 *>(dst + row) = v;
+      }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// M2L in float32 for orders up to 8 ((p+1)^2 <= 81) on 16x16x4 matrix-core
+// tiles.  The same work items, operator ranges, XCD mapping and LDS operator
+// sharing as k_m2l_f32, but output rows 0..79 are 5 tiles of 16 and row 80 is
+// formed on the vector ALU, so no matrix work is spent on padding rows.  Wave
+// w owns targets 32w .. 32w+31 of the block as two 16-column halves; lane
+// (q = lane / 16, c = lane % 16) supplies operator row c of a tile and the
+// sources of targets c and c + 16.  In k-step s (21 per operator) lane group q
+// contracts k = 20q + s (s < 20) or 80 + q (s = 20): each lane's sources are
+// five float4 runs plus one shared float4.  Operator rows are stored
+// pre-permuted: LDS row 4s + q holds that k (80 output rows), followed by the
+// 84 row-80 entries.  Output tile registers: lane (q, c) holds rows 4q .. 4q+3
+// of its tile for its column.
+// ---------------------------------------------------------------------------
+template <int UNUSED>
+struct M2L16 {
+  static constexpr int NS = 21, RW = 80;
+  static constexpr int AROWS = 4 * NS;            // 84 k rows
+  static constexpr int AFL = AROWS * RW + AROWS;  // floats per staged operator (6804)
+  static constexpr int AV = AFL / 4;              // float4 per staged operator (1701)
+  static constexpr int AR = (AV + 255) / 256;     // float4 per thread
+};
+
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2)))
+k_m2l16_f32(const float *__restrict__ M, float *__restrict__ Out, const float *__restrict__ Tab,
+            const int4 *__restrict__ lists, M2LPlan a) {
+  using G = M2L16<0>;
+  constexpr int NS = G::NS, RW = G::RW, AFL = G::AFL, AV = G::AV, AR = G::AR;
+  __shared__ float As[2][AFL];
+
+  // ---- work item (blocks of one XCD take consecutive items)
+  const int nitems = a.nsplit * a.ngroups * a.tile_run;
+  const int bid = blockIdx.x;
+  const int item = (bid & 7) * (nitems >> 3) + (bid >> 3);
+  const int tile = a.tile0 + item % a.tile_run;
+  const int split = item / a.tile_run;
+  int l = a.lmin;
+  while (l < a.d && tile >= a.tiles_start[l + 1]) ++l;
+  const int tl = tile - a.tiles_start[l];
+  const int cls = tl & 7, chunk = tl >> 3;
+  const int o0 = split * kListLen / a.nsplit, o1 = (split + 1) * kListLen / a.nsplit;
+  const int nit = o1 - o0;
+
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int q = lane >> 4, c = lane & 15;
+  const int nl = 1 << l;
+  const int64_t ntg = int64_t(1) << (3 * (l - 1));
+  const int64_t Pw = (int64_t)chunk * kM2LTile + wave * 32;
+  // waves whose 32 targets are all empty (levels with few boxes) skip the matrix work
+  const bool wave_busy = Pw < ntg;
+  int64_t Ph[2];
+  bool valid[2];
+  int tx[2] = {0, 0}, ty[2] = {0, 0}, tz[2] = {0, 0};
+#pragma unroll
+  for (int hf = 0; hf < 2; ++hf) {
+    Ph[hf] = Pw + 16 * hf + c;
+    valid[hf] = Ph[hf] < ntg;
+    if (valid[hf]) unmorton((uint32_t)(8 * Ph[hf] + cls), tx[hf], ty[hf], tz[hf]);
+  }
+  const int64_t off = level_offset(l);
+  const int4 *lst = lists + cls * kListLen;
+
+  // source row of target half hf for operator iteration it, or the all-zero row
+  auto src_row = [&](int it, int hf) -> int64_t {
+    const int4 v = lst[o0 + it];
+    int sx = tx[hf] - v.x, sy = ty[hf] - v.y, sz = tz[hf] - v.z;
+    bool ok = valid[hf];
+    if (a.periodic) {
+      sx = (sx + 4 * nl) & (nl - 1);
+      sy = (sy + 4 * nl) & (nl - 1);
+      sz = (sz + 4 * nl) & (nl - 1);
+    } else {
+      ok = ok && (unsigned)sx < (unsigned)nl && (unsigned)sy < (unsigned)nl && (unsigned)sz < (unsigned)nl;
+    }
+    return ok ? off + (int64_t)morton(sx, sy, sz) : a.zbox;
+  };
+  // b[hf][s]: k = 20q + s (s < 20), 80 + q (s = 20)
+  auto load_b = [&](int it, float (*b)[NS]) {
+#pragma unroll
+    for (int hf = 0; hf < 2; ++hf) {
+      const float *row = M + src_row(it, hf) * a.KS;
+      const floatx4 *qv = reinterpret_cast<const floatx4 *>(row + 20 * q);
+#pragma unroll
+      for (int i = 0; i < 5; ++i) {
+        const floatx4 v = qv[i];
+        b[hf][4 * i + 0] = v[0];
+        b[hf][4 * i + 1] = v[1];
+        b[hf][4 * i + 2] = v[2];
+        b[hf][4 * i + 3] = v[3];
+      }
+      const floatx4 t4 = *reinterpret_cast<const floatx4 *>(row + 80);
+      b[hf][20] = q == 0 ? t4[0] : (q == 1 ? t4[1] : (q == 2 ? t4[2] : t4[3]));
+    }
+  };
+  auto a_src = [&](int it) {
+    const int4 v = lst[o0 + it];
+    return reinterpret_cast<const floatx4 *>(Tab + (int64_t)v.w * AFL);
+  };
+  auto load_a = [&](int it, floatx4 *r) {
+    const floatx4 *src = a_src(it);
+#pragma unroll
+    for (int i = 0; i < AR; ++i) {
+      const int e = threadIdx.x + 256 * i;
+      if (e < AV) r[i] = src[e];
+    }
+  };
+  auto store_a = [&](int buf, const floatx4 *r) {
+    floatx4 *dst = reinterpret_cast<floatx4 *>(As[buf]);
+#pragma unroll
+    for (int i = 0; i < AR; ++i) {
+      const int e = threadIdx.x + 256 * i;
+      if (e < AV) dst[e] = r[i];
+    }
+  };
+
+  floatx4 acc[5][2];
+#pragma unroll
+  for (int t = 0; t < 5; ++t)
+#pragma unroll
+    for (int hf = 0; hf < 2; ++hf) acc[t][hf] = floatx4{0.f, 0.f, 0.f, 0.f};
+  float r80[2] = {0.f, 0.f};
+
+  float b0[2][NS], b1[2][NS];
+  floatx4 ast[AR];
+  load_a(0, ast);
+  store_a(0, ast);
+  load_a(min(1, nit - 1), ast);
+  load_b(0, b0);
+  __syncthreads();
+
+  // one operator iteration: stage the next operator, prefetch the next
+  // sources, then the matrix-core steps on LDS buffer it & 1
+  auto body = [&](int it, float (*bc)[NS], float (*bn)[NS]) {
+    const int buf = it & 1;
+    store_a(buf ^ 1, ast);
+    load_a(min(it + 2, nit - 1), ast);
+    load_b(min(it + 1, nit - 1), bn);
+    const float *Ar = As[buf] + q * RW + c;          // k row 4s + q, output row 16t + c
+    const float *A80 = As[buf] + G::AROWS * RW + q;  // row-80 entry of k row 4s + q
+    if (wave_busy) {
+#pragma unroll
+      for (int s2 = 0; s2 < NS; ++s2) {
+#pragma unroll
+        for (int t = 0; t < 5; ++t) {
+          const float av = Ar[4 * s2 * RW + 16 * t];
+#pragma unroll
+          for (int hf = 0; hf < 2; ++hf)
+            acc[t][hf] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bc[hf][s2], acc[t][hf], 0, 0, 0);
+        }
+        const float a80 = A80[4 * s2];
+        r80[0] += a80 * bc[0][s2];
+        r80[1] += a80 * bc[1][s2];
+      }
+    }
+    __syncthreads();
+  };
+  for (int it = 0; it < nit; it += 2) {
+    body(it, b0, b1);
+    if (it + 1 < nit) body(it + 1, b1, b0);
+  }
+
+  // row 80: sum the four k groups (lanes c, c + 16, c + 32, c + 48) in group order
+#pragma unroll
+  for (int hf = 0; hf < 2; ++hf) {
+    const float v0 = __shfl(r80[hf], c, 64), v1 = __shfl(r80[hf], c + 16, 64);
+    const float v2 = __shfl(r80[hf], c + 32, 64), v3 = __shfl(r80[hf], c + 48, 64);
+    r80[hf] = ((v0 + v1) + v2) + v3;
+  }
+  // ---- results: rows 16t + 4q .. +3 for target 16 hf + c; row 80 and the zero pad by group 0
+#pragma unroll
+  for (int hf = 0; hf < 2; ++hf) {
+    if (!valid[hf]) continue;
+    const int64_t tb = off + 8 * Ph[hf] + cls;
+    float *dst = Out + ((int64_t)split * a.nbox + tb) * a.KS;
+#pragma unroll
+    for (int t = 0; t < 5; ++t) *reinterpret_cast<floatx4 *>(dst + 16 * t + 4 * q) = acc[t][hf];
+    if (q == 0) {
+      *reinterpret_cast<floatx4 *>(dst + 80) = floatx4{r80[hf], 0.f, 0.f, 0.f};
+      *reinterpret_cast<floatx4 *>(dst + 84) = floatx4{0.f, 0.f, 0.f, 0.f};
+    }
+  }
+}
+
+// L[b] = sum over operator ranges s (in order) of the partial locals, for the
+// boxes [b0, b1) of the M2L levels.
+__global__ void k_m2l_reduce(const floatx4 *__restrict__ part, floatx4 *__restrict__ L, int64_t v0, int64_t v1,
+                             int64_t stride, int nsplit) {
+  for (int64_t i = v0 + blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < v1; i += (int64_t)gridDim.x * blockDim.x) {
+    floatx4 s = part[i];
+    for (int k = 1; k < nsplit; ++k) s += part[i + k * stride];
+    L[i] = s;
+  }
+}
+
+// ---- float32 M2L plan: tiles of 128 targets, row groups of 96, operator ranges
+void m2l32_plan(int p, int d, int periodic, int n_cu, M2LPlan &a) {
+  a.K = (p + 1) * (p + 1);
+  if (a.K <= 81) {
+    // 16x16x4 kernel: one operator chunk of 21 steps (k <= 83), rows read up to k = 83
+    a.ns = 21;
+    a.nkc = 1;
+    a.KS = 88;
+  } else {
+    a.ns = 40;
+    a.nkc = (a.K + kM2LKC - 1) / kM2LKC;
+    a.KS = a.nkc * kM2LKC;
+  }
+  a.ngroups = a.ns == 21 ? 1 : (a.K + kM2LRowGroup - 1) / kM2LRowGroup;
+  a.d = d;
+  a.periodic = periodic;
+  a.lmin = periodic ? 1 : 2;
+  a.nbox = level_offset(d + 1);
+  a.zbox = a.nbox;
+  a.ntiles = 0;
+  for (int l = 0; l <= 8; ++l) a.tiles_start[l] = 0;
+  for (int l = a.lmin; l <= d; ++l) {
+    a.tiles_start[l] = a.ntiles;
+    const int64_t ntg = int64_t(1) << (3 * (l - 1));
+    a.ntiles += (int)(8 * ((ntg + kM2LTile - 1) / kM2LTile));
+  }
+  if (d + 1 <= 8) a.tiles_start[d + 1] = a.ntiles;
+  a.tile0 = 0;
+  a.tile_run = a.ntiles;
+  // operator ranges: the split count minimising a fluid makespan model with
+  // two resident blocks per CU, in units of one operator step of a block:
+  //   max(work / slots + item / 2, item) + overhead * splits,
+  // item = 189 nkc / s steps; the overhead (prologue of an item, partial
+  // write and reduction) was fitted on the 1M-atom, depth-5 workload.
+  a.nsplit = 1;
+  if (a.ntiles > 0) {
+    const double slots = 2.0 * (n_cu > 0 ? n_cu : 256);
+    const double work = (double)a.ntiles * a.ngroups * kListLen * a.nkc;
+    const double over = kListLen * a.nkc / 32.0;
+    double best = 1e300;
+    for (int s = 1; s <= kM2LMaxSplit; ++s) {
+      const double item = (double)kListLen * a.nkc / s;
+      const double cost = std::max(work / slots + 0.5 * item, item) + over * s;
+      if (cost < best - 1e-9) {
+        best = cost;
+        a.nsplit = s;
+      }
+    }
+  }
+}
+
+void launch_m2l_f32(const float *M, float *L, float *part, const float *Tab, const int4 *lists, const M2LPlan &plan,
+                    int lev_lo, int lev_hi, hipStream_t st) {
+  lev_lo = std::max(lev_lo, plan.lmin);
+  lev_hi = std::min(lev_hi, plan.d);
+  if (plan.ntiles == 0 || lev_lo > lev_hi) return;
+  M2LPlan a = plan;
+  a.tile0 = plan.tiles_start[lev_lo];
+  a.tile_run = plan.tiles_start[lev_hi + 1] - a.tile0;  // a multiple of 8 (8 classes per chunk)
+  if (a.tile_run <= 0) return;
+  const int blocks = a.nsplit * a.ngroups * a.tile_run;
+  float *out = a.nsplit > 1 ? part : L;
+  if (a.ns == 21)
+    hipLaunchKernelGGL(k_m2l16_f32, dim3(blocks), dim3(256), 0, st, M, out, Tab, lists, a);
+  else
+    hipLaunchKernelGGL(k_m2l_f32<40>, dim3(blocks), dim3(256), 0, st, M, out, Tab, lists, a);
+  if (a.nsplit > 1) {
+    const int64_t b0 = level_offset(lev_lo), b1 = level_offset(lev_hi + 1);
+    const int64_t v0 = b0 * a.KS / 4, v1 = b1 * a.KS / 4;
+    const int64_t n = v1 - v0;
+    const int grid = (int)std::min<int64_t>((n + 255) / 256, 4096);
+    hipLaunchKernelGGL(k_m2l_reduce, dim3(grid), dim3(256), 0, st, reinterpret_cast<const floatx4 *>(part),
+                       reinterpret_cast<floatx4 *>(L), v0, v1, a.nbox * a.KS / 4, a.nsplit);
+  }
+}
+
+// Host layout of the float32 M2L operator table: [slot][row group][chunk][r][96]
+// where LDS row r = 2s + h of a chunk holds k = 8(s/4) + 4h + s%4.
+void m2l32_table(const M2LPlan &a, int slot, const double *Tv, float *dst) {
+  if (a.ns == 21) {
+    // k_m2l16_f32: [slot][84 k rows (4s + q)][80 output rows], then [84] row-80 entries
+    using G = M2L16<0>;
+    const int K = a.K;
+    float *blk = dst + (size_t)slot * G::AFL;
+    for (int r = 0; r < G::AROWS; ++r) {
+      const int s = r >> 2, q = r & 3;
+      const int k = s < 20 ? 20 * q + s : 80 + q;
+      for (int i = 0; i <= G::RW; ++i) {
+        const float v = (i < K && k < K) ? (float)Tv[(size_t)i * K + k] : 0.f;
+        if (i < G::RW) blk[(size_t)r * G::RW + i] = v;
+        else blk[(size_t)G::AROWS * G::RW + r] = v;
+      }
+    }
+    return;
+  }
+  const int K = a.K, KC = 2 * a.ns;
+  for (int g = 0; g < a.ngroups; ++g)
+    for (int c = 0; c < a.nkc; ++c)
+      for (int r = 0; r < KC; ++r) {
+        const int s = r >> 1, h = r & 1;
+        const int k = c * kM2LKC + 8 * (s >> 2) + 4 * h + (s & 3);
+        float *row = dst + ((((size_t)slot * a.ngroups + g) * a.nkc + c) * KC + r) * kM2LRowGroup;
+        for (int i = 0; i < kM2LRowGroup; ++i) {
+          const int orow = g * kM2LRowGroup + i;
+          row[i] = (orow < K && k < K) ? (float)Tv[(size_t)orow * K + k] : 0.f;
+        }
+      }
+}
+
+size_t m2l32_table_size(const M2LPlan &a, int nslots) {
+  if (a.ns == 21) return (size_t)nslots * M2L16<0>::AFL;
+  return (size_t)nslots * a.ngroups * a.nkc * (2 * a.ns) * kM2LRowGroup;
+}
+
+}  // namespace mahi

@@ -45,12 +45,32 @@ class _Opts(ctypes.Structure):
 
 class _EvalArgs(ctypes.Structure):
     _fields_ = [("xyz", ctypes.c_void_p), ("energy", ctypes.c_void_p), ("forces", ctypes.c_void_p),
-                ("dvdl", ctypes.c_void_p), ("potential", ctypes.c_void_p), ("flags", ctypes.c_uint32)]
+                ("dvdl", ctypes.c_void_p), ("potential", ctypes.c_void_p), ("flags", ctypes.c_uint32),
+                ("dedq", ctypes.c_void_p), ("energy_qi", ctypes.c_void_p), ("dvdl_qi", ctypes.c_void_p)]
+
+
+class _CorrectArgs(ctypes.Structure):
+    _fields_ = [("xyz", ctypes.c_void_p), ("potential", ctypes.c_void_p), ("energy", ctypes.c_void_p),
+                ("forces", ctypes.c_void_p), ("dvdl", ctypes.c_void_p), ("dedq", ctypes.c_void_p),
+                ("flags", ctypes.c_uint32)]
+
+
+def _init_torch_runtime():
+    """PyTorch ships its own HIP runtime.  Two runtimes share the GPU in one
+    process only when torch's initialises first (initialised afterwards it
+    finds no device), so start it before this library's when a GPU is visible."""
+    try:
+        import torch
+    except ImportError:
+        return
+    if torch.cuda.is_available():
+        torch.cuda.init()
 
 
 def load(path: str = LIB_PATH) -> ctypes.CDLL:
     if not os.path.exists(path):
         raise ImportError(f"libmahi.so not built at {path}; run python -m paper_2410_01754_amd.build")
+    _init_torch_runtime()
     lib = ctypes.CDLL(path)
     vp = ctypes.c_void_p
     lib.mahi_create.argtypes = [ctypes.POINTER(vp), ctypes.POINTER(_Box), ctypes.c_int64,
@@ -82,6 +102,15 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.mahi_stage_name.restype = ctypes.c_char_p
     lib.mahi_debug_copy.argtypes = [vp, ctypes.c_int, vp, ctypes.c_int64]
     lib.mahi_debug_copy.restype = ctypes.c_int
+    lib.mahi_set_form_charges.argtypes = [vp, ctypes.POINTER(ctypes.c_double)]
+    lib.mahi_set_form_charges.restype = ctypes.c_int
+    lib.mahi_correct.argtypes = [vp, ctypes.POINTER(_CorrectArgs)]
+    lib.mahi_correct.restype = ctypes.c_int
+    dp = ctypes.POINTER(ctypes.c_double)
+    lib.mahi_lambda_tilde.argtypes = [ctypes.c_int, dp, dp]
+    lib.mahi_lambda_tilde.restype = ctypes.c_int
+    lib.mahi_dlambda.argtypes = [ctypes.c_int, dp, dp, dp]
+    lib.mahi_dlambda.restype = ctypes.c_int
     return lib
 
 
@@ -117,6 +146,26 @@ def _ptr(a: np.ndarray, t):
     return a.ctypes.data_as(ctypes.POINTER(t))
 
 
+def lambda_tilde(lambdas) -> np.ndarray:
+    """Weights of the 2^L forms of a binary site from its L original lambdas (mahi_lambda_tilde)."""
+    lam = np.ascontiguousarray(lambdas, dtype=np.float64)
+    out = np.zeros(1 << lam.shape[0])
+    _check(lib().mahi_lambda_tilde(int(lam.shape[0]), _ptr(lam, ctypes.c_double), _ptr(out, ctypes.c_double)))
+    return out
+
+
+def dlambda(lambdas, dvdl) -> np.ndarray:
+    """dE/dlambda_k of a binary site from its per-form dE/dlambda-tilde (mahi_dlambda)."""
+    lam = np.ascontiguousarray(lambdas, dtype=np.float64)
+    g = np.ascontiguousarray(dvdl, dtype=np.float64)
+    if g.shape[0] != 1 << lam.shape[0]:
+        raise ValueError("dvdl must have 2^len(lambdas) entries")
+    out = np.zeros(lam.shape[0])
+    _check(lib().mahi_dlambda(int(lam.shape[0]), _ptr(lam, ctypes.c_double), _ptr(g, ctypes.c_double),
+                              _ptr(out, ctypes.c_double)))
+    return out
+
+
 class Mahi:
     """One MAHI evaluator: a cubic box, N charges and their titratable sites.
 
@@ -137,6 +186,7 @@ class Mahi:
         fq = np.ascontiguousarray(np.concatenate([np.asarray(c, dtype=np.float64).reshape(-1) for _, c in sites])
                                   if len(sites) else np.zeros(0), dtype=np.float64)
         self.n_forms = int(fps.sum())
+        self.n_form_charges = int(fq.shape[0])
         self._keep = (q, fps, aps, atoms, fq)
         box = _Box(float(edge), 1 if periodic else 0)
         st = _Sites(len(sites), _ptr(fps, ctypes.c_int32), _ptr(aps, ctypes.c_int32), _ptr(atoms, ctypes.c_int32),
@@ -164,8 +214,16 @@ class Mahi:
             raise ValueError("lambda_tilde has the wrong length")
         _check(self._lib.mahi_set_lambda(self._h, _ptr(lt, ctypes.c_double)), self._h)
 
-    def eval(self, xyz, forces: bool = True, dvdl: bool = True, potential: bool = False):
-        """Host-memory evaluation; returns dict(energy, forces, dvdl, potential)."""
+    def set_form_charges(self, form_charges):
+        """Replace every form charge (flat, the layout given at creation: per site form-major, atom-minor)."""
+        fq = np.ascontiguousarray(form_charges, dtype=np.float64).reshape(-1)
+        if fq.shape[0] != self.n_form_charges:
+            raise ValueError("form_charges has the wrong length")
+        _check(self._lib.mahi_set_form_charges(self._h, _ptr(fq, ctypes.c_double)), self._h)
+
+    def eval(self, xyz, forces: bool = True, dvdl: bool = True, potential: bool = False, dedq: bool = False,
+             qi: bool = False):
+        """Host-memory evaluation; returns dict(energy, forces, dvdl, potential, dedq, energy_qi, dvdl_qi)."""
         x = np.ascontiguousarray(xyz, dtype=self.dtype)
         if x.shape != (self.n, 3):
             raise ValueError("xyz must have shape (N, 3)")
@@ -173,17 +231,49 @@ class Mahi:
         F = np.zeros((self.n, 3), dtype=self.dtype) if forces else None
         dv = np.zeros(self.n_forms) if (dvdl and self.n_forms) else None
         pot = np.zeros(self.n, dtype=self.dtype) if potential else None
-        args = _EvalArgs(x.ctypes.data, E.ctypes.data, None if F is None else F.ctypes.data,
-                         None if dv is None else dv.ctypes.data, None if pot is None else pot.ctypes.data, 0)
+        dq = np.zeros(self.n_form_charges) if (dedq and self.n_forms) else None
+        Eqi = np.zeros(1) if qi else None
+        dvqi = np.zeros(self.n_forms) if (qi and self.n_forms) else None
+        a = lambda v: None if v is None else v.ctypes.data  # noqa: E731
+        args = _EvalArgs(x.ctypes.data, E.ctypes.data, a(F), a(dv), a(pot), 0, a(dq), a(Eqi), a(dvqi))
         _check(self._lib.mahi_eval(self._h, ctypes.byref(args)), self._h)
-        return {"energy": float(E[0]), "forces": F, "dvdl": dv, "potential": pot}
+        return {"energy": float(E[0]), "forces": F, "dvdl": dv, "potential": pot, "dedq": dq,
+                "energy_qi": None if Eqi is None else float(Eqi[0]), "dvdl_qi": dvqi}
 
     def eval_device(self, xyz_ptr: int, energy_ptr: int, forces_ptr: int = 0, dvdl_ptr: int = 0,
-                    potential_ptr: int = 0):
+                    potential_ptr: int = 0, dedq_ptr: int = 0, energy_qi_ptr: int = 0, dvdl_qi_ptr: int = 0):
         """Asynchronous evaluation on device pointers (e.g. torch tensor data_ptr())."""
         args = _EvalArgs(xyz_ptr, energy_ptr or None, forces_ptr or None, dvdl_ptr or None, potential_ptr or None,
-                         MAHI_DEVICE_IO)
+                         MAHI_DEVICE_IO, dedq_ptr or None, energy_qi_ptr or None, dvdl_qi_ptr or None)
         _check(self._lib.mahi_eval(self._h, ctypes.byref(args)), self._h)
+
+    def correct(self, xyz, potential, forces=None, dvdl: bool = True, dedq: bool = False):
+        """Site correction on a potential from another solver (host memory; mahi_correct).
+
+        potential: [N] coulomb_k * charge-scaled potential.  forces: optional [N, 3]
+        array of the same type as xyz; the correction is added to it in place.
+        Returns dict(energy, dvdl, dedq, forces)."""
+        x = np.ascontiguousarray(xyz, dtype=self.dtype)
+        pot = np.ascontiguousarray(potential, dtype=self.dtype)
+        if x.shape != (self.n, 3) or pot.shape != (self.n,):
+            raise ValueError("xyz must have shape (N, 3) and potential (N,)")
+        if forces is not None and (forces.dtype != self.dtype or forces.shape != (self.n, 3)
+                                   or not forces.flags.c_contiguous):
+            raise ValueError("forces must be a C-contiguous (N, 3) array of the context's type")
+        E = np.zeros(1)
+        dv = np.zeros(self.n_forms) if (dvdl and self.n_forms) else None
+        dq = np.zeros(self.n_form_charges) if (dedq and self.n_forms) else None
+        a = lambda v: None if v is None else v.ctypes.data  # noqa: E731
+        args = _CorrectArgs(x.ctypes.data, pot.ctypes.data, E.ctypes.data, a(forces), a(dv), a(dq), 0)
+        _check(self._lib.mahi_correct(self._h, ctypes.byref(args)), self._h)
+        return {"energy": float(E[0]), "dvdl": dv, "dedq": dq, "forces": forces}
+
+    def correct_device(self, xyz_ptr: int, potential_ptr: int, energy_ptr: int, forces_ptr: int = 0,
+                       dvdl_ptr: int = 0, dedq_ptr: int = 0):
+        """Asynchronous site correction on device pointers."""
+        args = _CorrectArgs(xyz_ptr, potential_ptr, energy_ptr or None, forces_ptr or None, dvdl_ptr or None,
+                            dedq_ptr or None, MAHI_DEVICE_IO)
+        _check(self._lib.mahi_correct(self._h, ctypes.byref(args)), self._h)
 
     def profile_begin(self, max_evals: int):
         _check(self._lib.mahi_profile_begin(self._h, int(max_evals)), self._h)

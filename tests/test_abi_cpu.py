@@ -85,3 +85,48 @@ def test_create_without_gpu_reports_device_error():
         pytest.skip("a GPU is present")
     r, msg = _create()
     assert r == -3
+
+
+# ------------------------------------------------------------------ binary multi-form sites (host only)
+
+@pytest.mark.parametrize("n", [1, 2, 3, 4])
+def test_lambda_tilde_matches_oracle(n):
+    from oracle import lmap
+    rng = np.random.default_rng(100 + n)
+    for _ in range(5):
+        lam = rng.random(n)
+        assert np.allclose(mb.lambda_tilde(lam), lmap.lambda_tilde(lam), rtol=1e-15, atol=1e-16)
+
+
+@pytest.mark.parametrize("n", [1, 2, 3, 4])
+def test_dlambda_matches_oracle(n):
+    from oracle import lmap
+    rng = np.random.default_rng(200 + n)
+    for _ in range(5):
+        lam = rng.random(n)
+        g = rng.normal(size=1 << n)
+        assert np.allclose(mb.dlambda(lam, g), lmap.dlambda_from_dtilde(lam, g), rtol=1e-13, atol=1e-14)
+
+
+def test_lambda_helpers_validate():
+    lib = mb.load()
+    d = ctypes.POINTER(ctypes.c_double)
+    lam = np.array([0.3, float("nan")])
+    out = np.zeros(4)
+    assert lib.mahi_lambda_tilde(0, mb._ptr(lam, ctypes.c_double), mb._ptr(out, ctypes.c_double)) == -4
+    assert lib.mahi_lambda_tilde(5, mb._ptr(lam, ctypes.c_double), mb._ptr(out, ctypes.c_double)) == -4
+    assert lib.mahi_lambda_tilde(2, mb._ptr(lam, ctypes.c_double), mb._ptr(out, ctypes.c_double)) == -1
+    assert lib.mahi_lambda_tilde(1, None, mb._ptr(out, ctypes.c_double)) == -1
+    g = np.zeros(4)
+    assert lib.mahi_dlambda(2, mb._ptr(np.array([0.3, 0.4]), ctypes.c_double), ctypes.cast(None, d),
+                            mb._ptr(out, ctypes.c_double)) == -1
+    g[2] = float("inf")
+    assert lib.mahi_dlambda(2, mb._ptr(np.array([0.3, 0.4]), ctypes.c_double), mb._ptr(g, ctypes.c_double),
+                            mb._ptr(out, ctypes.c_double)) == -1
+
+
+def test_null_context_is_rejected():
+    lib = mb.load()
+    assert lib.mahi_correct(None, None) == -1
+    assert lib.mahi_set_form_charges(None, None) == -1
+    assert lib.mahi_eval(None, None) == -1

@@ -1,0 +1,265 @@
+"""Parity of the derivative, charge-interpolation and correction-only paths
+with the CPU oracle (run on an MI355X).
+
+* dE/dq per form charge (general formulation, every weight and form charge an
+  independent variable), the charge-interpolated energy and its dE/dlambda-tilde;
+* mahi_correct: the site correction applied to a potential from another
+  solver (here the oracle's exact potential, and the library's own);
+* the torch.autograd binding and central differences of the float64 GPU path.
+Relative RMS ||a - b|| / ||b|| throughout; tolerances as in the main parity
+tests (rounding at depth 0 in float64, 2e-4 at order 8, 1e-5 at order 12).
+"""
+import os
+
+import numpy as np
+import pytest
+
+from oracle import ewald, hi, kernels
+from synth import make_config, make_system
+
+pytestmark = pytest.mark.gpu
+HERE = os.path.dirname(os.path.abspath(__file__))
+KE = hi.KE_DEFAULT
+
+
+def rel(a, b):
+    a, b = np.asarray(a, float), np.asarray(b, float)
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def flat(dedq_list):
+    return np.concatenate([np.asarray(d).reshape(-1) for d in dedq_list])
+
+
+def evaluator(system, precision, order, depth, **kw):
+    import paper_2410_01754_amd as pkg
+    print(f"[gpu] {system.name} N={system.n_atoms} p={order} d={depth} prec={precision}", flush=True)
+    return pkg.from_system(system, precision=precision, order=order, depth=depth, **kw)
+
+
+def gpu_full(system, precision, order, depth):
+    m = evaluator(system, precision, order, depth)
+    out = m.eval(system.x, potential=True, dedq=True, qi=True)
+    m.close()
+    return out
+
+
+def small_periodic(seed=31, edge=2.4):
+    nw = int(33.4 * edge ** 3)
+    return make_system(nw, edge, True, [6, 8, 5, 7], [2, 3, 2, 4], qrange=(-0.9, 0.9), total_step=None,
+                       clustered=True, simplex=True, depth=2, seed=seed, name=f"periodic{edge}")
+
+
+def open_oracle(s):
+    Phi, G = kernels.open_dense(s.x)
+    E, F, dv, dq = hi.hi_dense(s.q, s.sites, Phi, G)
+    Eqi, dvqi = hi.qi_dense(s.q, s.sites, Phi)
+    return E, F, dv, flat(dq), Eqi, dvqi, Phi, G
+
+
+# ------------------------------------------------------------------ dE/dq and charge interpolation
+
+def test_dedq_qi_open_depth0_float64():
+    """Depth 0: all pairs direct, so every output reproduces the oracle to rounding."""
+    s = make_config(0)
+    E, F, dv, dq, Eqi, dvqi, _, _ = open_oracle(s)
+    g = gpu_full(s, 64, 8, 0)
+    assert rel(g["dedq"], dq) <= 1e-12
+    assert abs(g["energy_qi"] - Eqi) <= 1e-12 * abs(Eqi)
+    assert rel(g["dvdl_qi"], dvqi) <= 1e-12
+
+
+@pytest.mark.parametrize("prec", [64, 32])
+def test_dedq_qi_open_p8(prec):
+    s = make_config(0)
+    E, F, dv, dq, Eqi, dvqi, _, _ = open_oracle(s)
+    g = gpu_full(s, prec, 8, 2)
+    e = (rel(g["dedq"], dq), abs(g["energy_qi"] - Eqi) / abs(Eqi), rel(g["dvdl_qi"], dvqi))
+    print("open d2 p8 dedq/Eqi/dvdl_qi", prec, e)
+    assert max(e) <= 2e-4
+
+
+def test_dedq_qi_periodic_small_float64():
+    s = small_periodic(seed=36)
+    E, F, dv, dq, Eqi, dvqi = hi.hi_periodic(s.x, s.q, s.sites, s.box, qi=True)
+    g = gpu_full(s, 64, 12, 2)
+    e = (rel(g["dedq"], flat(dq)), abs(g["energy_qi"] - Eqi) / abs(Eqi), rel(g["dvdl_qi"], dvqi))
+    print("periodic d2 p12 dedq/Eqi/dvdl_qi", e)
+    assert max(e) <= 1e-5
+
+
+def _golden(k, field):
+    path = os.path.join(HERE, "golden", f"config{k}_oracle.npz")
+    if not os.path.exists(path):
+        pytest.skip(f"{path} not generated")
+    gd = np.load(path)
+    if field not in gd.files:
+        pytest.skip(f"{path} holds no {field}")
+    return gd
+
+
+@pytest.mark.parametrize("prec,order,tol", [(32, 8, 2e-4), (64, 8, 2e-4), (64, 16, 1e-6)])
+def test_config1_dedq_qi(prec, order, tol):
+    gd = _golden(1, "dedq")
+    s = make_config(1)
+    g = gpu_full(s, prec, order, 4)
+    e = (rel(g["dedq"], gd["dedq"]), abs(g["energy_qi"] - gd["energy_qi"][0]) / abs(gd["energy_qi"][0]),
+         rel(g["dvdl_qi"], gd["dvdl_qi"]))
+    print(f"config1 prec={prec} p={order}: dedq {e[0]:.3e} E_qi {e[1]:.3e} dvdl_qi {e[2]:.3e}")
+    assert max(e) <= tol
+
+
+def test_config2_dedq_qi():
+    gd = _golden(2, "dedq")
+    s = make_config(2)
+    g = gpu_full(s, 32, 8, 5)
+    e = (rel(g["dedq"], gd["dedq"]), abs(g["energy_qi"] - gd["energy_qi"][0]) / abs(gd["energy_qi"][0]),
+         rel(g["dvdl_qi"], gd["dvdl_qi"]))
+    print(f"config2 fp32 p=8: dedq {e[0]:.3e} E_qi {e[1]:.3e} dvdl_qi {e[2]:.3e}")
+    assert max(e) <= 2e-4
+
+
+# ------------------------------------------------------------------ correction on another solver's potential
+
+def _correct(s, precision, order, pot, F_base):
+    m = evaluator(s, precision, order, 0)
+    F = np.ascontiguousarray(F_base, dtype=m.dtype).copy()
+    out = m.correct(s.x, pot, forces=F, dedq=True)
+    m.close()
+    return out
+
+
+@pytest.mark.parametrize("prec,tol", [(64, 1e-12), (32, 1e-5)])
+def test_correct_open_on_exact_potential(prec, tol):
+    """Open boundaries: the site kernel is the exact 1/r, so the QI result of the
+    oracle plus the correction is the oracle's HI result."""
+    s = make_config(0)
+    E, F, dv, dq, Eqi, dvqi, Phi, G = open_oracle(s)
+    qt, _ = hi.scaled_charges(s.n_atoms, s.q, s.sites)
+    Eq, Fq, _, _ = hi.hi_dense(qt, [], Phi, G)
+    c = _correct(s, prec, 8, KE * (Phi @ qt), Fq)
+    e = (abs(Eq + c["energy"] - E) / abs(E), rel(c["forces"], F), rel(c["dvdl"], dv), rel(c["dedq"], dq))
+    print("correct open", prec, e)
+    assert max(e) <= tol
+
+
+def test_correct_periodic_on_exact_potential():
+    """Periodic: the potential is the oracle's Ewald sum; the correction's pair
+    kernel is the 27 nearest images plus the order-16 lattice remainder."""
+    s = small_periodic(seed=37)
+    E, F, dv, dq = hi.hi_periodic(s.x, s.q, s.sites, s.box)
+    qt, _ = hi.scaled_charges(s.n_atoms, s.q, s.sites)
+    phi, fld = ewald.field(s.x, qt, s.box)
+    Eq = 0.5 * KE * qt @ phi
+    Fq = KE * qt[:, None] * fld
+    c = _correct(s, 64, 16, KE * phi, Fq)
+    e = (abs(Eq + c["energy"] - E) / abs(E), rel(c["forces"], F), rel(c["dvdl"], dv), rel(c["dedq"], flat(dq)))
+    print("correct periodic p16", e)
+    # bounded by the order-16 lattice truncation (the whole-system float64 error at
+    # order 16 is below 1e-7 in the order sweep)
+    assert max(e) <= 1e-7
+
+
+@pytest.mark.parametrize("prec", [64, 32])
+def test_correct_on_own_potential_matches_eval(prec):
+    """Plain FMM of the scaled charges + mahi_correct on its potential = mahi_eval."""
+    import paper_2410_01754_amd as pkg
+    s = small_periodic(seed=38)
+    m = evaluator(s, prec, 8, 2)
+    full = m.eval(s.x, potential=True, dedq=True, qi=True)
+    qt, _ = hi.scaled_charges(s.n_atoms, s.q, s.sites)
+    plain = pkg.Mahi(s.box, True, qt, [], order=8, depth=2, precision=prec)
+    p = plain.eval(s.x, potential=True)
+    plain.close()
+    F = p["forces"].copy()
+    c = m.correct(s.x, p["potential"], forces=F, dedq=True)
+    m.close()
+    tol = 1e-13 if prec == 64 else 2e-6
+    assert abs(full["energy_qi"] - p["energy"]) <= 1e-14 * abs(p["energy"])
+    assert abs(p["energy"] + c["energy"] - full["energy"]) <= 1e-13 * abs(full["energy"])
+    assert rel(F, full["forces"]) <= tol
+    assert rel(c["dvdl"], full["dvdl"]) <= tol and rel(c["dedq"], full["dedq"]) <= tol
+
+
+def test_set_form_charges_matches_new_context():
+    """Changing the form charges in place gives the same result as a context created with them."""
+    import paper_2410_01754_amd as pkg
+    s = small_periodic(seed=39)
+    rng = np.random.default_rng(3)
+    sites2 = [(st.atoms, st.charges + 0.05 * rng.normal(size=st.charges.shape)) for st in s.sites]
+    m = evaluator(s, 64, 8, 2)
+    m.set_form_charges(np.concatenate([c.reshape(-1) for _, c in sites2]))
+    a = m.eval(s.x, dedq=True)
+    m.close()
+    m2 = pkg.Mahi(s.box, True, s.q, sites2, order=8, depth=2, precision=64)
+    m2.set_lambda(s.lam_flat())
+    b = m2.eval(s.x, dedq=True)
+    m2.close()
+    assert a["energy"] == b["energy"]
+    assert np.array_equal(a["forces"], b["forces"]) and np.array_equal(a["dedq"], b["dedq"])
+
+
+# ------------------------------------------------------------------ autograd and finite differences
+
+def test_autograd_matches_oracle_depth0():
+    import torch
+    from paper_2410_01754_amd.autograd import MahiEnergy, flat_form_charges
+    s = make_config(0)
+    E, F, dv, dq, _, _, _, _ = open_oracle(s)
+    dev = torch.device("cuda:0")
+    m = evaluator(s, 64, 8, 0, stream=torch.cuda.current_stream().cuda_stream)
+    x = torch.tensor(s.x, dtype=torch.float64, device=dev, requires_grad=True)
+    lt = torch.tensor(s.lam_flat(), dtype=torch.float64, requires_grad=True)
+    fq = torch.tensor(flat_form_charges(s), dtype=torch.float64, requires_grad=True)
+    e = MahiEnergy.apply(x, lt, fq, m)
+    (2.0 * e).backward()
+    m.close()
+    assert abs(e.item() - E) <= 1e-12 * abs(E)
+    assert rel(x.grad.cpu().numpy(), -2.0 * F) <= 1e-12
+    assert rel(lt.grad.cpu().numpy(), 2.0 * dv) <= 1e-12
+    assert rel(fq.grad.cpu().numpy(), 2.0 * dq) <= 1e-12
+
+
+def test_central_differences_float64_gpu():
+    """P7 on the float64 GPU path (open, depth 2, order 16): forces, dE/dlambda-tilde
+    and dE/dq against central differences of the GPU energy.  The energy is
+    quadratic in the weights and form charges, so those differences are exact
+    up to rounding and the order-16 truncation (the analytic derivatives use
+    the potential, the difference its symmetrised form); in x the step is
+    1e-4 nm."""
+    import paper_2410_01754_amd as pkg
+    s = make_config(0)
+    m = evaluator(s, 64, 16, 2)
+    base = m.eval(s.x.astype(np.float64), dedq=True)
+    lam = s.lam_flat()
+    for k in (0, 3, 6):
+        lp, lm = lam.copy(), lam.copy()
+        lp[k] += 1e-3
+        lm[k] -= 1e-3
+        m.set_lambda(lp)
+        ep = m.eval(s.x)["energy"]
+        m.set_lambda(lm)
+        em = m.eval(s.x)["energy"]
+        assert abs((ep - em) / 2e-3 - base["dvdl"][k]) <= 1e-6 * np.abs(base["dvdl"]).max()
+    m.set_lambda(lam)
+    fq = np.concatenate([st.charges.reshape(-1) for st in s.sites])
+    for k in (0, 7, 13):
+        qp, qm = fq.copy(), fq.copy()
+        qp[k] += 1e-4
+        qm[k] -= 1e-4
+        m.set_form_charges(qp)
+        ep = m.eval(s.x)["energy"]
+        m.set_form_charges(qm)
+        em = m.eval(s.x)["energy"]
+        assert abs((ep - em) / 2e-4 - base["dedq"][k]) <= 1e-6 * np.abs(base["dedq"]).max()
+    m.set_form_charges(fq)
+    x = s.x.astype(np.float64)
+    site0 = s.sites[0].atoms[0]
+    for i, d in ((site0, 0), (5, 1), (500, 2)):
+        xp, xm = x.copy(), x.copy()
+        xp[i, d] += 1e-4
+        xm[i, d] -= 1e-4
+        fd = -(m.eval(xp)["energy"] - m.eval(xm)["energy"]) / 2e-4
+        assert abs(fd - base["forces"][i, d]) <= 1e-5 * np.abs(base["forces"]).max()
+    m.close()
+    del pkg
