@@ -1424,8 +1424,10 @@ template <class T>
 void launch_p2m(const Atom4<T> *sorted, const int *start, int nleaf, int p, int KS, T *Mleaf, double *qds, const Geom *g,
                 int d, hipStream_t st) {
   const int K = (p + 1) * (p + 1);
+  // atoms per LDS pass: at most 32 (a typical leaf in one pass, small enough
+  // LDS for many one-wave blocks per CU)
   int chunk = (int)(16384 / (K * sizeof(T)));
-  if (chunk > 64) chunk = 64;
+  if (chunk > 32) chunk = 32;
   if (chunk < 1) chunk = 1;
   if (p == 8)
     hipLaunchKernelGGL((k_p2m<T, 8>), dim3(nleaf), dim3(64), chunk * K * sizeof(T), st, sorted, start, p, K, KS, chunk,

@@ -187,17 +187,21 @@ k_m2l_f32(const float *__restrict__ M, float *__restrict__ Out, const float *__r
 // (q = lane / 16, c = lane % 16) supplies operator row c of a tile and the
 // sources of targets c and c + 16.  In k-step s (21 per operator) lane group q
 // contracts k = 20q + s (s < 20) or 80 + q (s = 20): each lane's sources are
-// five float4 runs plus one shared float4.  Operator rows are stored
-// pre-permuted: LDS row 4s + q holds that k (80 output rows), followed by the
-// 84 row-80 entries.  Output tile registers: lane (q, c) holds rows 4q .. 4q+3
-// of its tile for its column.
+// five float4 runs plus one shared float4.  The operator is stored in the
+// order the lanes read it, so that one ds_read_b128 gives a lane the values of
+// four consecutive k-steps of one row tile (8 MFMAs): steps 0..19 as
+// [s / 4][q][t][c][s % 4], step 20 as [q][t][c], then the row-80 entries as
+// [q][24 steps] (value A[k(s, q)][16 t + c] = T[16 t + c][k]).  The next group
+// of four steps is read while the current one is multiplied.  Output tile
+// registers: lane (q, c) holds rows 4q .. 4q+3 of its tile for its column.
 // ---------------------------------------------------------------------------
 template <int UNUSED>
 struct M2L16 {
   static constexpr int NS = 21, RW = 80;
-  static constexpr int AROWS = 4 * NS;            // 84 k rows
-  static constexpr int AFL = AROWS * RW + AROWS;  // floats per staged operator (6804)
-  static constexpr int AV = AFL / 4;              // float4 per staged operator (1701)
+  static constexpr int TAIL = 5 * 4 * 5 * 16 * 4;  // steps 0..19: [g][q][t][c][4]  (6400)
+  static constexpr int R80 = TAIL + 4 * 5 * 16;     // step 20: [q][t][c]            (6720)
+  static constexpr int AFL = R80 + 4 * 24;          // row 80: [q][24 steps]         (6816)
+  static constexpr int AV = AFL / 4;              // float4 per staged operator (1704)
   static constexpr int AR = (AV + 255) / 256;     // float4 per thread
 };
 
@@ -205,8 +209,8 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2)))
 k_m2l16_f32(const float *__restrict__ M, float *__restrict__ Out, const float *__restrict__ Tab,
             const int4 *__restrict__ lists, M2LPlan a) {
   using G = M2L16<0>;
-  constexpr int NS = G::NS, RW = G::RW, AFL = G::AFL, AV = G::AV, AR = G::AR;
-  __shared__ float As[2][AFL];
+  constexpr int NS = G::NS, AFL = G::AFL, AV = G::AV, AR = G::AR;
+  __shared__ __attribute__((aligned(16))) float As[2][AFL];
 
   // ---- work item (blocks of one XCD take consecutive items)
   const int nitems = a.nsplit * a.ngroups * a.tile_run;
@@ -315,22 +319,48 @@ k_m2l16_f32(const float *__restrict__ M, float *__restrict__ Out, const float *_
     store_a(buf ^ 1, ast);
     load_a(min(it + 2, nit - 1), ast);
     load_b(min(it + 1, nit - 1), bn);
-    const float *Ar = As[buf] + q * RW + c;          // k row 4s + q, output row 16t + c
-    const float *A80 = As[buf] + G::AROWS * RW + q;  // row-80 entry of k row 4s + q
+    const floatx4 *A4 = reinterpret_cast<const floatx4 *>(As[buf]) + q * 80 + c;  // + (20 g + t) * 16
+    const float *At = As[buf] + G::TAIL + q * 80 + c;                              // + 16 t
+    const floatx4 *A80 = reinterpret_cast<const floatx4 *>(As[buf] + G::R80 + 24 * q);
     if (wave_busy) {
+      floatx4 avn[5], a80n;
 #pragma unroll
-      for (int s2 = 0; s2 < NS; ++s2) {
+      for (int t = 0; t < 5; ++t) avn[t] = A4[t * 16];
+      a80n = A80[0];
 #pragma unroll
-        for (int t = 0; t < 5; ++t) {
-          const float av = Ar[4 * s2 * RW + 16 * t];
+      for (int g = 0; g < 5; ++g) {
+        floatx4 av[5];
 #pragma unroll
-          for (int hf = 0; hf < 2; ++hf)
-            acc[t][hf] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bc[hf][s2], acc[t][hf], 0, 0, 0);
+        for (int t = 0; t < 5; ++t) av[t] = avn[t];
+        const floatx4 a80 = a80n;
+        if (g < 4) {
+#pragma unroll
+          for (int t = 0; t < 5; ++t) avn[t] = A4[(20 * (g + 1) + t) * 16];
+          a80n = A80[g + 1];
         }
-        const float a80 = A80[4 * s2];
-        r80[0] += a80 * bc[0][s2];
-        r80[1] += a80 * bc[1][s2];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const int s2 = 4 * g + j;
+#pragma unroll
+          for (int t = 0; t < 5; ++t)
+#pragma unroll
+            for (int hf = 0; hf < 2; ++hf)
+              acc[t][hf] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[t][j], bc[hf][s2], acc[t][hf], 0, 0, 0);
+          r80[0] += a80[j] * bc[0][s2];
+          r80[1] += a80[j] * bc[1][s2];
+        }
       }
+      float av[5];
+#pragma unroll
+      for (int t = 0; t < 5; ++t) av[t] = At[16 * t];
+      const float a80 = As[buf][G::R80 + 24 * q + 20];
+#pragma unroll
+      for (int t = 0; t < 5; ++t)
+#pragma unroll
+        for (int hf = 0; hf < 2; ++hf)
+          acc[t][hf] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[t], bc[hf][20], acc[t][hf], 0, 0, 0);
+      r80[0] += a80 * bc[0][20];
+      r80[1] += a80 * bc[1][20];
     }
     __syncthreads();
   };
@@ -452,19 +482,22 @@ void launch_m2l_f32(const float *M, float *L, float *part, const float *Tab, con
 // where LDS row r = 2s + h of a chunk holds k = 8(s/4) + 4h + s%4.
 void m2l32_table(const M2LPlan &a, int slot, const double *Tv, float *dst) {
   if (a.ns == 21) {
-    // k_m2l16_f32: [slot][84 k rows (4s + q)][80 output rows], then [84] row-80 entries
+    // k_m2l16_f32, per slot: steps 0..19 [s/4][q][t][c][s%4], step 20 [q][t][c], row 80 [q][24]
     using G = M2L16<0>;
     const int K = a.K;
     float *blk = dst + (size_t)slot * G::AFL;
-    for (int r = 0; r < G::AROWS; ++r) {
-      const int s = r >> 2, q = r & 3;
-      const int k = s < 20 ? 20 * q + s : 80 + q;
-      for (int i = 0; i <= G::RW; ++i) {
-        const float v = (i < K && k < K) ? (float)Tv[(size_t)i * K + k] : 0.f;
-        if (i < G::RW) blk[(size_t)r * G::RW + i] = v;
-        else blk[(size_t)G::AROWS * G::RW + r] = v;
-      }
-    }
+    auto T = [&](int i, int k) { return (i < K && k < K) ? (float)Tv[(size_t)i * K + k] : 0.f; };
+    for (int q = 0; q < 4; ++q)
+      for (int t = 0; t < 5; ++t)
+        for (int c = 0; c < 16; ++c) {
+          for (int g = 0; g < 5; ++g)
+            for (int j = 0; j < 4; ++j)
+              blk[((((size_t)g * 4 + q) * 5 + t) * 16 + c) * 4 + j] = T(16 * t + c, 20 * q + 4 * g + j);
+          blk[G::TAIL + ((size_t)q * 5 + t) * 16 + c] = T(16 * t + c, 80 + q);
+        }
+    for (int q = 0; q < 4; ++q)
+      for (int s = 0; s < 24; ++s)
+        blk[G::R80 + 24 * q + s] = s < 20 ? T(80, 20 * q + s) : (s == 20 ? T(80, 80 + q) : 0.f);
     return;
   }
   const int K = a.K, KC = 2 * a.ns;
