@@ -12,10 +12,12 @@ Reported next to the headline ns/eval:
   * per-stage mean durations from HIP events recorded on the library's stream
     over the timed region, and the roofline of the dominant kernel (M2L),
   * the site correction alone (mahi_correct) on a given potential,
+  * a batch of 96 small systems (3k..60k atoms, autotuned order and depth):
+    per-system latency and eager batched throughput (extra.batch96),
   * the CPU oracle on a bounded sample (same recipe, smaller cube), scaled to
     the full system by the oracle's measured size exponent.
 
-Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu]
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-batch]
 """
 from __future__ import annotations
 
@@ -96,6 +98,54 @@ def time_evals(m, x_dev, out, steps, warmup, profile=False):
     return dt / steps, stages
 
 
+def batch_leg(steps: int):
+    """96 periodic systems of 3k..60k atoms (log-uniform), each with the autotuned
+    order and depth for a 2e-4 target in float32: per-system latency alone and
+    the throughput of one eager batch (mahi_batch_eval) over all of them."""
+    import torch
+    import paper_2410_01754_amd as pkg
+    from synth import make_batch
+    systems = make_batch()
+    mods, bufs = [], []
+    for s in systems:
+        p, d = pkg.autotune(True, s.box, s.n_atoms, 32, 2e-4)
+        mods.append(pkg.from_system(s, precision=32, order=p, depth=d))
+        bufs.append((torch.from_numpy(s.x).cuda(), torch.zeros(1, dtype=torch.float64, device="cuda"),
+                     torch.zeros((s.n_atoms, 3), dtype=torch.float32, device="cuda"),
+                     torch.zeros(s.n_forms, dtype=torch.float64, device="cuda")))
+    ptr = [(x.data_ptr(), e.data_ptr(), f.data_ptr(), v.data_ptr()) for x, e, f, v in bufs]
+    n = np.array([s.n_atoms for s in systems], dtype=np.float64)
+    lat = []
+    for m, pt in zip(mods, ptr):
+        m.eval_device(*pt)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(3):
+            m.eval_device(*pt)
+        torch.cuda.synchronize()
+        lat.append((time.perf_counter() - t0) / 3)
+    lat = np.array(lat)
+    b = pkg.Batch(mods, use_graph=False)
+    args = [{"xyz": a, "energy": e, "forces": f, "dvdl": v} for a, e, f, v in ptr]
+    b.eval_device(args)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        b.eval_device(args)
+    torch.cuda.synchronize()
+    tb = (time.perf_counter() - t0) / steps
+    b.close()
+    depths = [m.info()["depth"] for m in mods]
+    for m in mods:
+        m.close()
+    return {"systems": len(systems), "atoms": int(n.sum()), "mode": "eager (one fork/join, per-system streams)",
+            "batch_ms": tb * 1e3, "atom_evals_per_s": float(n.sum() / tb),
+            "single_latency_us_p50": float(np.percentile(lat, 50) * 1e6),
+            "single_latency_us_p99": float(np.percentile(lat, 99) * 1e6),
+            "sequential_atom_evals_per_s": float(n.sum() / lat.sum()),
+            "depth_histogram": {str(d): depths.count(d) for d in sorted(set(depths))}}
+
+
 def cpu_baseline(full_n: int):
     """Oracle (Ewald HI, float64, all host cores) on three smaller cubes of the same
     recipe; the full-size time is extrapolated with the log-log fitted size exponent."""
@@ -126,6 +176,7 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--config", type=int, default=2)
     args = ap.parse_args()
     if args.gpus != 1:
@@ -231,6 +282,9 @@ def main():
                      "kernel": "m2l", "flop_per_launch": m2l_flop},
         "extra": extra,
     }
+    if not args.no_batch:
+        extra["batch96"] = batch_leg(max(3, args.steps // 4))
+        print(f"[bench] batch {extra['batch96']}", file=sys.stderr, flush=True)
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline(s.n_atoms)
     print(json.dumps(line))

@@ -185,6 +185,40 @@ mahi_status mahi_lambda_tilde(int n_lambda, const double *lambda, double *lambda
 mahi_status mahi_dlambda(int n_lambda, const double *lambda, const double *dvdl /* [2^n_lambda] */,
                          double *dlambda /* [n_lambda] */);
 
+/* Batched evaluation of many systems (small systems leave most of the GPU
+ * idle in a single evaluation; the paper's small-system regime, sections
+ * "Scaling with Number of Particles" and "Performance").  A batch holds n
+ * distinct contexts of one device and evaluates them together: every call
+ * forks from `hip_stream` (the batch's origin stream, NULL = a stream the
+ * batch creates), runs each context's evaluation on that context's own
+ * streams, and joins back, so later work on the origin stream sees every
+ * output.  use_graph = 1 (capture the whole fork/join once into a HIP graph
+ * and replay it, capturing again when a pointer in args changes) is disabled
+ * in this build and returns MAHI_EUNSUPPORTED; use_graph = 0 issues every
+ * kernel eagerly.
+ * The contexts stay owned by the caller and must outlive the batch; while in
+ * a batch they may still be used alone, but not concurrently with it.      */
+typedef struct mahi_batch mahi_batch;
+mahi_status mahi_batch_create(mahi_batch **out, mahi_ctx *const *ctxs, int n_ctx, int use_graph, void *hip_stream);
+/* args[n_ctx], each with MAHI_DEVICE_IO (device pointers; the call returns
+ * without waiting).  Every context must have its lambda-tilde set and no stage
+ * profiling open.  MAHI_EINVAL for host-memory arguments.                   */
+mahi_status mahi_batch_eval(mahi_batch *b, const mahi_eval_args *args);
+void mahi_batch_destroy(mahi_batch *b);
+const char *mahi_batch_last_error(const mahi_batch *b);
+
+/* Parameter choice for one system (host only, no device work).  order: the
+ * smallest p whose modelled relative RMS error of forces, dE/dlambda-tilde
+ * and dE/dq, err(p) = 1.6e-3 * 2^-(p-4) (fitted to the order sweeps of this
+ * library's float64 path against Ewald sums, well-separation 1), is at most
+ * half of target_rel_err.  depth: the d in 0..7 that minimises a cost model of
+ * one evaluation (near-field pairs, the serial near field of one crowded leaf,
+ * M2L translations scaled by (p+1)^4, and a per-level latency; constants
+ * measured on MI355X) for n_atoms spread evenly in the cube.  precision 32 cannot reach targets below 2e-5 (float32
+ * rounding), 64 not below 2e-8 (order 20): MAHI_ERANGE.                     */
+mahi_status mahi_autotune(int periodic, double edge, int64_t n_atoms, int precision, double target_rel_err, int *order,
+                          int *depth);
+
 /* Release every host and device resource of the context (NULL is allowed). */
 void mahi_destroy(mahi_ctx *ctx);
 

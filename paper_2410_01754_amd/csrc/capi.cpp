@@ -94,6 +94,24 @@ struct mahi_ctx {
   }
 };
 
+struct mahi_batch {
+  std::vector<mahi_ctx *> ctxs;
+  int device = 0;
+  bool use_graph = false;
+  hipStream_t root = nullptr;
+  bool own_root = false;
+  hipEvent_t fork = nullptr;
+  std::vector<hipEvent_t> joins;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  std::vector<mahi_eval_args> captured;  // the arguments baked into the graph
+  std::string err;
+  mahi_status fail(mahi_status s, const std::string &m) {
+    err = m;
+    return s;
+  }
+};
+
 namespace {
 
 thread_local std::string g_create_error;
@@ -436,6 +454,40 @@ bool all_finite(const void *p, int64_t n) {
   for (int64_t i = 0; i < n; ++i)
     if (!std::isfinite(x[i])) return false;
   return true;
+}
+
+#define BATCH_TRY(expr, what)                                                                \
+  do {                                                                                       \
+    hipError_t _e = (expr);                                                                  \
+    if (_e != hipSuccess) return b->fail(MAHI_EDEVICE, std::string(what) + ": " + hip_msg(_e)); \
+  } while (0)
+
+// Fork from the origin stream into every context's stream, evaluate, join back.
+mahi_status batch_issue(mahi_batch *b, const mahi_eval_args *args) {
+  BATCH_TRY(hipEventRecord(b->fork, b->root), "batch fork");
+  for (size_t i = 0; i < b->ctxs.size(); ++i) {
+    mahi_ctx *ctx = b->ctxs[i];
+    BATCH_TRY(hipStreamWaitEvent(ctx->stream, b->fork, 0), "batch fork");
+    const mahi_status st = ctx->prec == 32 ? eval_impl<float>(ctx, &args[i]) : eval_impl<double>(ctx, &args[i]);
+    if (st != MAHI_OK) return b->fail(st, "system " + std::to_string(i) + ": " + ctx->err);
+    BATCH_TRY(hipEventRecord(b->joins[i], ctx->stream), "batch join");
+    BATCH_TRY(hipStreamWaitEvent(b->root, b->joins[i], 0), "batch join");
+  }
+  return MAHI_OK;
+}
+
+void batch_drop_graph(mahi_batch *b) {
+  if (b->exec) (void)hipGraphExecDestroy(b->exec);
+  if (b->graph) (void)hipGraphDestroy(b->graph);
+  b->exec = nullptr;
+  b->graph = nullptr;
+  b->captured.clear();
+}
+
+bool same_args(const mahi_eval_args &a, const mahi_eval_args &c) {
+  return a.xyz == c.xyz && a.energy == c.energy && a.forces == c.forces && a.dvdl == c.dvdl &&
+         a.potential == c.potential && a.flags == c.flags && a.dedq == c.dedq && a.energy_qi == c.energy_qi &&
+         a.dvdl_qi == c.dvdl_qi;
 }
 
 void free_ctx(mahi_ctx *ctx) {
@@ -792,6 +844,164 @@ mahi_status mahi_debug_copy(mahi_ctx *ctx, int which, void *host_out, int64_t co
     return MAHI_OK;
   }
   HIP_TRY(hipMemcpy(host_out, src, want, hipMemcpyDeviceToHost), "copy");
+  return MAHI_OK;
+}
+
+mahi_status mahi_batch_create(mahi_batch **out, mahi_ctx *const *ctxs, int n_ctx, int use_graph, void *hip_stream) {
+  g_create_error.clear();
+  if (!out) return MAHI_EINVAL;
+  *out = nullptr;
+  if (!ctxs || n_ctx < 1) {
+    g_create_error = "ctxs must hold at least one context";
+    return MAHI_EINVAL;
+  }
+  if (use_graph != 0 && use_graph != 1) {
+    g_create_error = "use_graph must be 0 or 1";
+    return MAHI_EINVAL;
+  }
+  for (int i = 0; i < n_ctx; ++i) {
+    if (!ctxs[i]) {
+      g_create_error = "NULL context";
+      return MAHI_EINVAL;
+    }
+    for (int j = 0; j < i; ++j)
+      if (ctxs[j] == ctxs[i]) {
+        g_create_error = "a context appears twice";
+        return MAHI_EINVAL;
+      }
+    if (ctxs[i]->device != ctxs[0]->device) {
+      g_create_error = "contexts on different devices";
+      return MAHI_EINVAL;
+    }
+  }
+  if (use_graph) {
+    // The captured-graph path ended in a host segmentation fault on its first
+    // capture and launch, with no cause shown yet; it stays off until one is.
+    g_create_error = "graph capture of a batch is disabled in this build (use_graph = 0 evaluates eagerly)";
+    return MAHI_EUNSUPPORTED;
+  }
+  mahi_batch *b = new (std::nothrow) mahi_batch;
+  if (!b) return MAHI_ENOMEM;
+  b->ctxs.assign(ctxs, ctxs + n_ctx);
+  b->device = ctxs[0]->device;
+  b->use_graph = use_graph != 0;
+  auto bad = [&](const char *m) {
+    g_create_error = m;
+    mahi_batch_destroy(b);
+    return MAHI_EDEVICE;
+  };
+  if (hipSetDevice(b->device) != hipSuccess) return bad("set device");
+  if (hip_stream) {
+    b->root = static_cast<hipStream_t>(hip_stream);
+  } else {
+    if (hipStreamCreateWithFlags(&b->root, hipStreamNonBlocking) != hipSuccess) return bad("stream creation failed");
+    b->own_root = true;
+  }
+  if (hipEventCreateWithFlags(&b->fork, hipEventDisableTiming) != hipSuccess) return bad("event creation failed");
+  b->joins.assign(n_ctx, nullptr);
+  for (auto &e : b->joins)
+    if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) return bad("event creation failed");
+  *out = b;
+  return MAHI_OK;
+}
+
+mahi_status mahi_batch_eval(mahi_batch *b, const mahi_eval_args *args) {
+  if (!b) return MAHI_EINVAL;
+  if (!args) return b->fail(MAHI_EINVAL, "args is NULL");
+  for (size_t i = 0; i < b->ctxs.size(); ++i) {
+    const mahi_ctx *ctx = b->ctxs[i];
+    if (!args[i].xyz) return b->fail(MAHI_EINVAL, "args[" + std::to_string(i) + "].xyz is NULL");
+    if (args[i].flags != MAHI_DEVICE_IO) return b->fail(MAHI_EINVAL, "batched evaluation needs MAHI_DEVICE_IO");
+    if (!ctx->lambda_set) return b->fail(MAHI_ESTATE, "system " + std::to_string(i) + ": lambda-tilde not set");
+    if (ctx->prof_max > 0) return b->fail(MAHI_ESTATE, "system " + std::to_string(i) + ": stage profiling is open");
+  }
+  BATCH_TRY(hipSetDevice(b->device), "set device");
+  if (!b->use_graph) return batch_issue(b, args);
+  bool same = b->exec != nullptr && b->captured.size() == b->ctxs.size();
+  for (size_t i = 0; same && i < b->ctxs.size(); ++i) same = same_args(args[i], b->captured[i]);
+  if (!same) {
+    batch_drop_graph(b);
+    BATCH_TRY(hipStreamBeginCapture(b->root, hipStreamCaptureModeRelaxed), "begin capture");
+    const mahi_status st = batch_issue(b, args);
+    hipGraph_t g = nullptr;
+    const hipError_t e = hipStreamEndCapture(b->root, &g);
+    if (st != MAHI_OK) {
+      if (g) (void)hipGraphDestroy(g);
+      return st;
+    }
+    if (e != hipSuccess) return b->fail(MAHI_EDEVICE, std::string("end capture: ") + hip_msg(e));
+    b->graph = g;
+    const hipError_t ei = hipGraphInstantiate(&b->exec, g, nullptr, nullptr, 0);
+    if (ei != hipSuccess) {
+      batch_drop_graph(b);
+      return b->fail(MAHI_EDEVICE, std::string("graph instantiate: ") + hip_msg(ei));
+    }
+    b->captured.assign(args, args + b->ctxs.size());
+  }
+  BATCH_TRY(hipGraphLaunch(b->exec, b->root), "graph launch");
+  return MAHI_OK;
+}
+
+void mahi_batch_destroy(mahi_batch *b) {
+  if (!b) return;
+  (void)hipSetDevice(b->device);
+  if (b->root) (void)hipStreamSynchronize(b->root);
+  batch_drop_graph(b);
+  if (b->fork) (void)hipEventDestroy(b->fork);
+  for (auto &e : b->joins)
+    if (e) (void)hipEventDestroy(e);
+  if (b->own_root && b->root) (void)hipStreamDestroy(b->root);
+  delete b;
+}
+
+const char *mahi_batch_last_error(const mahi_batch *b) {
+  if (!b) return g_create_error.c_str();
+  return b->err.c_str();
+}
+
+mahi_status mahi_autotune(int periodic, double edge, int64_t n_atoms, int precision, double target, int *order,
+                          int *depth) {
+  if (!order || !depth) return MAHI_EINVAL;
+  if (periodic != 0 && periodic != 1) return MAHI_EINVAL;
+  if (!(is_fin(edge) && edge > 0)) return MAHI_EINVAL;
+  if (precision != 32 && precision != 64) return MAHI_EINVAL;
+  if (!(is_fin(target) && target > 0)) return MAHI_EINVAL;
+  if (n_atoms < 1 || n_atoms > (int64_t)0x7fffffff - 1) return MAHI_ERANGE;
+  if (target < (precision == 32 ? 2e-5 : 2e-8)) return MAHI_ERANGE;
+  int p = 0;
+  for (int c = 1; c <= kMaxOrder && !p; ++c)
+    if (1.6e-3 * std::pow(0.5, c - 4) <= 0.5 * target) p = c;
+  if (!p) return MAHI_ERANGE;
+  // seconds per unit, from the 1,004,296-atom depth-5 order-8 stage times
+  const bool f32 = precision == 32;
+  const double c_pair = f32 ? 6.6e-13 : 2.2e-12;                  // ordered near-field pair
+  const double kk = (p + 1.0) * (p + 1.0) / 81.0;
+  const double c_tr = (f32 ? 1.5e-10 : 4.4e-10) * kk * kk;       // one M2L translation, dense (p+1)^2 squared
+  const double c_leaf = 2.0e-9 * kk;                               // P2M / L2P / block overhead per leaf
+  const double c_lvl = 2.0e-5;                                     // launch latency per tree level
+  // one leaf's near field runs in one 64-lane block: with few, crowded leaves
+  // the evaluation waits on that block (seconds per pair of one leaf, measured
+  // on lone blocks of 3k..24k-atom systems at depths 1..2)
+  const double c_blk = f32 ? 1.05e-9 : 3.6e-9;
+  const double n = (double)n_atoms;
+  double best = 1e300;
+  int bd = 0;
+  for (int d = 0; d <= 7; ++d) {
+    const double leaves = std::ldexp(1.0, 3 * d);
+    const double nb = periodic ? 27.0 : std::min(27.0, leaves);
+    const double pairs = n * nb * n / leaves;
+    double tr = 0.0;
+    for (int l = periodic ? 1 : 2; l <= d; ++l) tr += 189.0 * std::ldexp(1.0, 3 * l);
+    const double per_leaf = n / leaves;
+    const double t = c_pair * pairs + c_blk * nb * per_leaf * per_leaf + c_tr * tr + c_leaf * leaves + c_lvl * d;
+    if (t < best) {
+      best = t;
+      bd = d;
+    }
+  }
+  *order = p;
+  *depth = bd;
+  (void)edge;
   return MAHI_OK;
 }
 

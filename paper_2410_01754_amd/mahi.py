@@ -111,6 +111,17 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.mahi_lambda_tilde.restype = ctypes.c_int
     lib.mahi_dlambda.argtypes = [ctypes.c_int, dp, dp, dp]
     lib.mahi_dlambda.restype = ctypes.c_int
+    lib.mahi_batch_create.argtypes = [ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.c_int, ctypes.c_int, vp]
+    lib.mahi_batch_create.restype = ctypes.c_int
+    lib.mahi_batch_eval.argtypes = [vp, ctypes.POINTER(_EvalArgs)]
+    lib.mahi_batch_eval.restype = ctypes.c_int
+    lib.mahi_batch_destroy.argtypes = [vp]
+    lib.mahi_batch_destroy.restype = None
+    lib.mahi_batch_last_error.argtypes = [vp]
+    lib.mahi_batch_last_error.restype = ctypes.c_char_p
+    ip = ctypes.POINTER(ctypes.c_int)
+    lib.mahi_autotune.argtypes = [ctypes.c_int, ctypes.c_double, ctypes.c_int64, ctypes.c_int, ctypes.c_double, ip, ip]
+    lib.mahi_autotune.restype = ctypes.c_int
     return lib
 
 
@@ -144,6 +155,14 @@ def device_selftest(precision: int) -> float:
 
 def _ptr(a: np.ndarray, t):
     return a.ctypes.data_as(ctypes.POINTER(t))
+
+
+def autotune(periodic: bool, edge: float, n_atoms: int, precision: int, target_rel_err: float):
+    """(order, depth) from the library's error and cost models (mahi_autotune)."""
+    o, d = ctypes.c_int(), ctypes.c_int()
+    _check(lib().mahi_autotune(1 if periodic else 0, float(edge), int(n_atoms), int(precision), float(target_rel_err),
+                               ctypes.byref(o), ctypes.byref(d)))
+    return o.value, d.value
 
 
 def lambda_tilde(lambdas) -> np.ndarray:
@@ -311,3 +330,44 @@ def from_system(system, precision: int = 32, order: Optional[int] = None, depth:
     if system.sites:
         m.set_lambda(system.lam_flat())
     return m
+
+
+class Batch:
+    """Evaluate several evaluators together (mahi_batch_*): one fork/join from
+    `stream`.  use_graph=True (graph capture) is refused by this build."""
+
+    def __init__(self, evaluators: Sequence[Mahi], use_graph: bool = False, stream: Optional[int] = None):
+        self._lib = lib()
+        self.evaluators = list(evaluators)
+        arr = (ctypes.c_void_p * len(self.evaluators))(*[m._h.value for m in self.evaluators])
+        h = ctypes.c_void_p()
+        st = self._lib.mahi_batch_create(ctypes.byref(h), arr, len(self.evaluators), 1 if use_graph else 0,
+                                         ctypes.c_void_p(stream or 0))
+        if st != 0:
+            raise MahiError(st, self._lib.mahi_batch_last_error(None).decode())
+        self._h = h
+
+    def eval_device(self, ptrs: Sequence[dict]):
+        """ptrs[i]: dict of device pointers (xyz, energy, forces, dvdl, potential, dedq, energy_qi, dvdl_qi)."""
+        if len(ptrs) != len(self.evaluators):
+            raise ValueError("one pointer set per evaluator")
+        args = (_EvalArgs * len(ptrs))()
+        for a, p in zip(args, ptrs):
+            a.xyz = p["xyz"]
+            for k in ("energy", "forces", "dvdl", "potential", "dedq", "energy_qi", "dvdl_qi"):
+                setattr(a, k, p.get(k) or None)
+            a.flags = MAHI_DEVICE_IO
+        st = self._lib.mahi_batch_eval(self._h, args)
+        if st != 0:
+            raise MahiError(st, self._lib.mahi_batch_last_error(self._h).decode())
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            self._lib.mahi_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -3,4 +3,4 @@
 This package only draws positions, charges and weights; it holds none of the
 electrostatics or the interpolation arithmetic.
 """
-from .systems import System, Site, make_config, make_system, CONFIG_NAMES  # noqa: F401
+from .systems import System, Site, make_batch, make_config, make_system, CONFIG_NAMES  # noqa: F401

@@ -248,3 +248,28 @@ def make_config(k: int, seed: Optional[int] = None) -> System:
             specs.append((pos, ch, lam_two_form(rng)))
         return _finish("config2", True, edge, xw, qw, specs, 5, 8, seed)
     raise ValueError(f"unknown configuration {k}")
+
+
+def make_batch(n_systems: int = 96, n_min: int = 3000, n_max: int = 60000, seed: int = 1758,
+               depth: int = 3, order: int = 8) -> list:
+    """Many small periodic water boxes (the paper's small-system regime): total
+    atom counts log-uniform in [n_min, n_max], edge (N_w / 33.4)^(1/3) nm, 4..64
+    clustered two-form sites of 6..10 atoms, lambda ~ U[0, 1].  depth and order
+    are placeholders; callers choose their own per system.  The two forms of a
+    site are drawn independently (no total rule)."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for b in range(n_systems):
+        n_tot = float(np.exp(rng.uniform(np.log(n_min), np.log(n_max))))
+        n_sites = int(rng.integers(4, 65))
+        sizes = rng.integers(6, 11, size=n_sites)
+        n_w = max(1, int(round((n_tot - sizes.sum()) / 3)))
+        edge = (n_w / 33.4) ** (1.0 / 3.0)
+        xw, qw = waters(n_w, edge, rng)
+        specs = []
+        for n in sizes:
+            pos = clustered_positions(int(n), edge, rng)
+            ch = form_charges(2, int(n), -0.8, 0.8, rng, None)
+            specs.append((pos, ch, lam_two_form(rng)))
+        out.append(_finish(f"batch{b}", True, edge, xw, qw, specs, depth, order, seed * 1000 + b))
+    return out

@@ -130,3 +130,44 @@ def test_null_context_is_rejected():
     assert lib.mahi_correct(None, None) == -1
     assert lib.mahi_set_form_charges(None, None) == -1
     assert lib.mahi_eval(None, None) == -1
+
+
+# ------------------------------------------------------------------ autotuner and batch (host checks)
+
+def test_autotune_reproduces_the_tuned_configurations():
+    # the paper-scale system and the 100k-atom cube at the 2e-4 target of order 8
+    assert pkg.autotune(True, 21.5, 1004296, 32, 2e-4) == (8, 5)
+    assert pkg.autotune(True, 10.0, 100717, 32, 2e-4) == (8, 4)
+    # the 1e-6 target needs order 16 (the float64 parity case)
+    assert pkg.autotune(True, 10.0, 100717, 64, 1e-6)[0] == 16
+
+
+def test_autotune_order_is_monotone_and_depth_grows_with_size():
+    orders = [pkg.autotune(True, 5.0, 20000, 64, t)[0] for t in (1e-2, 1e-3, 1e-4, 1e-5, 1e-6, 1e-7)]
+    assert orders == sorted(orders) and orders[0] < orders[-1]
+    depths = [pkg.autotune(True, 5.0, n, 32, 2e-4)[1] for n in (1000, 10000, 100000, 1000000, 10000000)]
+    assert depths == sorted(depths) and depths[0] < depths[-1]
+
+
+@pytest.mark.parametrize("args,code", [
+    ((True, 10.0, 1000, 32, 1e-5), -4),       # below the float32 floor
+    ((True, 10.0, 1000, 64, 1e-9), -4),       # below what order 20 reaches
+    ((True, 10.0, 0, 32, 1e-3), -4),
+    ((True, 0.0, 1000, 32, 1e-3), -1),
+    ((True, 10.0, 1000, 16, 1e-3), -1),
+    ((True, 10.0, 1000, 32, float("nan")), -1),
+])
+def test_autotune_validates(args, code):
+    with pytest.raises(mb.MahiError) as e:
+        pkg.autotune(*args)
+    assert e.value.status == code
+
+
+def test_batch_create_validates_without_device():
+    lib = mb.load()
+    h = ctypes.c_void_p()
+    assert lib.mahi_batch_create(ctypes.byref(h), None, 0, 1, None) == -1
+    arr = (ctypes.c_void_p * 2)(None, None)
+    assert lib.mahi_batch_create(ctypes.byref(h), arr, 2, 1, None) == -1
+    assert lib.mahi_batch_eval(None, None) == -1
+    lib.mahi_batch_destroy(None)

@@ -1,0 +1,117 @@
+"""Batched evaluation of many small systems and the autotuner (run on an MI355X).
+
+* A batch (eager fork/join; the captured-graph mode is disabled and its case
+  skipped) gives the same bits as evaluating each system alone, repeatedly,
+  after a change of lambda-tilde and with new output buffers.
+* Systems evaluated with the autotuned order and depth meet the accuracy
+  target against the oracle's Ewald sums.
+"""
+import numpy as np
+import pytest
+
+from oracle import hi
+from synth import make_batch
+
+pytestmark = pytest.mark.gpu
+
+
+def rel(a, b):
+    a, b = np.asarray(a, float), np.asarray(b, float)
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def _build(systems, precision=32, target=2e-4):
+    import paper_2410_01754_amd as pkg
+    mods = []
+    for s in systems:
+        p, d = pkg.autotune(True, s.box, s.n_atoms, precision, target)
+        print(f"[gpu] {s.name} N={s.n_atoms} p={p} d={d} prec={precision}", flush=True)
+        mods.append(pkg.from_system(s, precision=precision, order=p, depth=d))
+    return mods
+
+
+def _buffers(systems, dtype):
+    import torch
+    out = []
+    for s in systems:
+        out.append({"x": torch.from_numpy(s.x.astype(np.float32 if dtype == torch.float32 else np.float64)).cuda(),
+                    "E": torch.zeros(1, dtype=torch.float64, device="cuda"),
+                    "F": torch.zeros((s.n_atoms, 3), dtype=dtype, device="cuda"),
+                    "dv": torch.zeros(s.n_forms, dtype=torch.float64, device="cuda")})
+    return out
+
+
+def _ptrs(bufs):
+    return [{"xyz": b["x"].data_ptr(), "energy": b["E"].data_ptr(), "forces": b["F"].data_ptr(),
+             "dvdl": b["dv"].data_ptr()} for b in bufs]
+
+
+def _same(bufs, refs):
+    for b, r in zip(bufs, refs):
+        assert b["E"].item() == r["energy"]
+        assert np.array_equal(b["F"].cpu().numpy(), r["forces"])
+        assert np.array_equal(b["dv"].cpu().numpy(), r["dvdl"])
+
+
+@pytest.mark.parametrize("use_graph", [False, pytest.param(True, marks=pytest.mark.skip(
+    reason="graph capture of a batch is disabled: its first capture and launch ended in a host segmentation "
+           "fault whose cause is not yet shown"))])
+def test_batch_matches_single_evaluations(use_graph):
+    import torch
+    import paper_2410_01754_amd as pkg
+    systems = make_batch(n_systems=6, n_min=1500, n_max=8000, seed=77)
+    mods = _build(systems)
+    refs = [m.eval(s.x) for m, s in zip(mods, systems)]
+    bufs = _buffers(systems, torch.float32)
+    batch = pkg.Batch(mods, use_graph=use_graph)
+    for rep in range(3):
+        for b in bufs:
+            b["E"].zero_()
+            b["F"].zero_()
+            b["dv"].zero_()
+        torch.cuda.synchronize()
+        batch.eval_device(_ptrs(bufs))
+        torch.cuda.synchronize()
+        print(f"[gpu] batch graph={use_graph} replay {rep}", flush=True)
+        _same(bufs, refs)
+        # eager work between replays
+        torch.cuda.synchronize()
+        _ = (bufs[0]["F"] * 2.0).sum().item()
+    # new weights for system 0: a replay reads them from device memory
+    lam = systems[0].lam_flat().copy()
+    lam[0::2], lam[1::2] = lam[1::2].copy(), lam[0::2].copy()
+    mods[0].set_lambda(lam)
+    refs[0] = mods[0].eval(systems[0].x)
+    batch.eval_device(_ptrs(bufs))
+    torch.cuda.synchronize()
+    _same(bufs, refs)
+    # new output buffers: the batch captures again
+    bufs2 = _buffers(systems, torch.float32)
+    batch.eval_device(_ptrs(bufs2))
+    torch.cuda.synchronize()
+    _same(bufs2, refs)
+    batch.close()
+    for m in mods:
+        m.close()
+
+
+def test_autotuned_systems_meet_target():
+    systems = make_batch(n_systems=3, n_min=2000, n_max=6000, seed=78)
+    mods = _build(systems, precision=32, target=2e-4)
+    for m, s in zip(mods, systems):
+        g = m.eval(s.x)
+        E, F, dv, _ = hi.hi_periodic(s.x, s.q, s.sites, s.box)
+        e = (abs(g["energy"] - E) / abs(E), rel(g["forces"], F), rel(g["dvdl"], dv))
+        print(f"{s.name} N={s.n_atoms}: E {e[0]:.2e} F {e[1]:.2e} dVdl {e[2]:.2e}")
+        assert max(e) <= 2e-4
+        m.close()
+
+
+def test_batch_graph_mode_is_refused():
+    import paper_2410_01754_amd as pkg
+    systems = make_batch(n_systems=1, n_min=1500, n_max=2000, seed=79)
+    mods = _build(systems)
+    with pytest.raises(pkg.MahiError) as e:
+        pkg.Batch(mods, use_graph=True)
+    assert e.value.status == -6
+    mods[0].close()
