@@ -200,8 +200,12 @@ struct M2L16 {
   static constexpr int NS = 21, RW = 80;
   static constexpr int TAIL = 5 * 4 * 5 * 16 * 4;  // steps 0..19: [g][q][t][c][4]  (6400)
   static constexpr int R80 = TAIL + 4 * 5 * 16;     // step 20: [q][t][c]            (6720)
-  static constexpr int AFL = R80 + 4 * 24;          // row 80: [q][24 steps]         (6816)
-  static constexpr int AV = AFL / 4;              // float4 per staged operator (1704)
+  // row 80: [q][24 steps] at R80; zero padded to 7 float4 per thread of the
+  // block, so that staging needs no bounds test: a guarded load splits the
+  // loop into branches at which the compiler waits for every load in flight,
+  // prefetches included
+  static constexpr int AFL = 7 * 256 * 4;
+  static constexpr int AV = AFL / 4;              // float4 per staged operator (1792)
   static constexpr int AR = (AV + 255) / 256;     // float4 per thread
 };
 
@@ -272,8 +276,7 @@ k_m2l16_f32(const float *__restrict__ M, float *__restrict__ Out, const float *_
         b[hf][4 * i + 2] = v[2];
         b[hf][4 * i + 3] = v[3];
       }
-      const floatx4 t4 = *reinterpret_cast<const floatx4 *>(row + 80);
-      b[hf][20] = q == 0 ? t4[0] : (q == 1 ? t4[1] : (q == 2 ? t4[2] : t4[3]));
+      b[hf][20] = row[80 + q];  // a per-lane address, not a select on loaded data (which would wait for it)
     }
   };
   auto a_src = [&](int it) {
@@ -283,18 +286,12 @@ k_m2l16_f32(const float *__restrict__ M, float *__restrict__ Out, const float *_
   auto load_a = [&](int it, floatx4 *r) {
     const floatx4 *src = a_src(it);
 #pragma unroll
-    for (int i = 0; i < AR; ++i) {
-      const int e = threadIdx.x + 256 * i;
-      if (e < AV) r[i] = src[e];
-    }
+    for (int i = 0; i < AR; ++i) r[i] = src[threadIdx.x + 256 * i];
   };
   auto store_a = [&](int buf, const floatx4 *r) {
     floatx4 *dst = reinterpret_cast<floatx4 *>(As[buf]);
 #pragma unroll
-    for (int i = 0; i < AR; ++i) {
-      const int e = threadIdx.x + 256 * i;
-      if (e < AV) dst[e] = r[i];
-    }
+    for (int i = 0; i < AR; ++i) dst[threadIdx.x + 256 * i] = r[i];
   };
 
   floatx4 acc[5][2];
