@@ -196,6 +196,7 @@ mahi_status setup_device(mahi_ctx *ctx, const std::vector<double> &q_env, const 
   HIP_TRY(ctx->alloc(ctx->perm, sizeof(int) * N), "alloc perm");
   HIP_TRY(ctx->alloc(ctx->slot_of, sizeof(int) * N), "alloc slot map");
   HIP_TRY(ctx->alloc(ctx->count, sizeof(int) * nleaf), "alloc counts");
+  HIP_TRY(hipMemset(ctx->count, 0, sizeof(int) * nleaf), "zero counts");  // k_scan clears them after each use
   HIP_TRY(ctx->alloc(ctx->start, sizeof(int) * (nleaf + 1)), "alloc starts");
   HIP_TRY(ctx->alloc(ctx->qds, sizeof(double) * 5 * nleaf), "alloc moments");
   HIP_TRY(ctx->alloc(ctx->epart, sizeof(double) * p2p_blocks<T>(d)), "alloc energy partials");

@@ -200,12 +200,8 @@ __device__ __forceinline__ double rsqrt_t<double>(double x) {
 }
 
 // ---------------------------------------------------------------------------
-// Small utility kernels
+// Bounding cube of the coordinates (open boundaries)
 // ---------------------------------------------------------------------------
-__global__ void k_fill_i32(int *p, int v, int64_t n) {
-  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) p[i] = v;
-}
-
 template <class T>
 __global__ void k_bbox_partial(const T *__restrict__ xyz, int64_t n, double *__restrict__ part) {
   __shared__ double s[6][256];
@@ -302,23 +298,42 @@ __global__ void k_bin(const T *__restrict__ xyz, const T *__restrict__ qt, int64
 // counts are loaded coalesced into LDS, each thread scans 8 consecutive ones,
 // the block scans the thread sums (wave scans, then the 16 wave sums) and the
 // round's total carries into the next round.  start[nleaf] receives the total.
-__global__ void __launch_bounds__(1024) k_scan(const int *__restrict__ count, int *__restrict__ start, int nleaf) {
-  constexpr int R = 8192, PER = 8;
-  __shared__ int buf[R + R / 32];  // padded: element i at i + i / 32
+// Exclusive prefix sum of the leaf counts in one block: thread t owns 32
+// consecutive leaves of a round of 32,768 (eight int4 loads and stores), the
+// block sums are scanned across waves.  The counts are cleared as they are
+// read, ready for the binning of the next evaluation (they start cleared).
+__global__ void __launch_bounds__(1024) k_scan(int *__restrict__ count, int *__restrict__ start, int nleaf) {
+  constexpr int PER = 32, R = 1024 * PER;
   __shared__ int wsum[16];
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
   int carry = 0;
   for (int r0 = 0; r0 < nleaf; r0 += R) {
-    const int nr = min(R, nleaf - r0);
-    for (int i = t; i < R; i += 1024) buf[i + i / 32] = i < nr ? count[r0 + i] : 0;
-    __syncthreads();
-    int v[PER], loc = 0;
+    const int base = r0 + t * PER;
+    const bool full = base + PER <= nleaf;
+    int v[PER];
+    if (full) {
+      int4 *c4 = reinterpret_cast<int4 *>(count + base);
 #pragma unroll
-    for (int k = 0; k < PER; ++k) {
-      const int i = t * PER + k;
-      v[k] = buf[i + i / 32];
-      loc += v[k];
+      for (int i = 0; i < PER / 4; ++i) {
+        const int4 x = c4[i];
+        v[4 * i] = x.x;
+        v[4 * i + 1] = x.y;
+        v[4 * i + 2] = x.z;
+        v[4 * i + 3] = x.w;
+      }
+#pragma unroll
+      for (int i = 0; i < PER / 4; ++i) c4[i] = make_int4(0, 0, 0, 0);
+    } else {
+#pragma unroll
+      for (int k = 0; k < PER; ++k) {
+        const bool in = base + k < nleaf;
+        v[k] = in ? count[base + k] : 0;
+        if (in) count[base + k] = 0;
+      }
     }
+    int loc = 0;
+#pragma unroll
+    for (int k = 0; k < PER; ++k) loc += v[k];
     int s = loc;
     for (int o = 1; o < 64; o <<= 1) {
       const int u = __shfl_up(s, o, 64);
@@ -332,20 +347,34 @@ __global__ void __launch_bounds__(1024) k_scan(const int *__restrict__ count, in
         const int u = __shfl_up(w, o, 64);
         if (lane >= o) w += u;
       }
-      if (lane < 16) wsum[lane] = w;  // inclusive wave prefix
+      if (lane < 16) wsum[lane] = w;  // inclusive prefix over waves
     }
     __syncthreads();
     int run = carry + s - loc + (wave > 0 ? wsum[wave - 1] : 0);
+    if (full) {
+      int4 *s4 = reinterpret_cast<int4 *>(start + base);
 #pragma unroll
-    for (int k = 0; k < PER; ++k) {
-      const int i = t * PER + k;
-      buf[i + i / 32] = run;
-      run += v[k];
+      for (int i = 0; i < PER / 4; ++i) {
+        int4 o;
+        o.x = run;
+        run += v[4 * i];
+        o.y = run;
+        run += v[4 * i + 1];
+        o.z = run;
+        run += v[4 * i + 2];
+        o.w = run;
+        run += v[4 * i + 3];
+        s4[i] = o;
+      }
+    } else {
+#pragma unroll
+      for (int k = 0; k < PER; ++k) {
+        if (base + k < nleaf) start[base + k] = run;
+        run += v[k];
+      }
     }
     carry += wsum[15];
-    __syncthreads();
-    for (int i = t; i < nr; i += 1024) start[r0 + i] = buf[i + i / 32];
-    __syncthreads();
+    __syncthreads();  // wsum is rewritten by the next round
   }
   if (t == 0) start[nleaf] = carry;
 }
@@ -1396,10 +1425,6 @@ static inline int grid_for(int64_t n, int bs) {
   return (int)g;
 }
 
-void launch_fill_i32(int *p, int v, int64_t n, hipStream_t st) {
-  hipLaunchKernelGGL(k_fill_i32, dim3(grid_for(n, 256)), dim3(256), 0, st, p, v, n);
-}
-
 template <class T>
 void launch_bbox(const T *xyz, int64_t n, double *part, int nblk, Geom *g, hipStream_t st) {
   hipLaunchKernelGGL(k_bbox_partial<T>, dim3(nblk), dim3(256), 0, st, xyz, n, part);
@@ -1410,8 +1435,8 @@ template <class T>
 void launch_tree(const T *xyz, const T *qt, int64_t n, const Geom *g, int d, int periodic, TreeBufs<T> b,
                  hipStream_t st) {
   const int nleaf = 1 << (3 * d);
-  // slot_of holds the in-leaf arrival ranks until k_leafsort writes the slots
-  launch_fill_i32(b.count, 0, nleaf, st);
+  // slot_of holds the in-leaf arrival ranks until k_leafsort writes the slots;
+  // count is zero on entry (cleared at creation and by every k_scan)
   hipLaunchKernelGGL(k_bin<T>, dim3(grid_for(n, 256)), dim3(256), 0, st, xyz, qt, n, g, d, periodic, b.key, b.slot_of,
                      b.count, b.packed);
   hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, st, b.count, b.start, nleaf);

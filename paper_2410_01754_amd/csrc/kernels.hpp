@@ -70,7 +70,6 @@ struct TreeBufs {
 };
 
 hipError_t upload_constants();
-void launch_fill_i32(int *p, int v, int64_t n, hipStream_t st);
 template <class T> void launch_bbox(const T *xyz, int64_t n, double *part, int nblk, Geom *g, hipStream_t st);
 template <class T>
 void launch_tree(const T *xyz, const T *qt, int64_t n, const Geom *g, int d, int periodic, TreeBufs<T> b, hipStream_t st);

@@ -213,7 +213,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2)))
 k_m2l16_f32(const float *__restrict__ M, float *__restrict__ Out, const float *__restrict__ Tab,
             const int4 *__restrict__ lists, M2LPlan a) {
   using G = M2L16<0>;
-  constexpr int NS = G::NS, AFL = G::AFL, AV = G::AV, AR = G::AR;
+  constexpr int NS = G::NS, AFL = G::AFL, AR = G::AR;
   __shared__ __attribute__((aligned(16))) float As[2][AFL];
 
   // ---- work item (blocks of one XCD take consecutive items)
