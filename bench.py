@@ -95,7 +95,8 @@ def time_evals(m, x_dev, out, steps, warmup, profile=False):
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     stages = m.profile_end()[0] if profile else None
-    return dt / steps, stages
+    per = m.profile_eval_times(steps) if profile else None
+    return dt / steps, stages, per
 
 
 def batch_leg(steps: int):
@@ -203,7 +204,7 @@ def main():
     m32 = pkg.from_system(s, precision=32, stream=stream)
     x32 = torch.from_numpy(s.x).to(dev)
     o32 = outputs(torch.float32, s.n_forms)
-    t32, stages = time_evals(m32, x32, o32, args.steps, args.warmup, profile=True)
+    t32, stages, per_eval = time_evals(m32, x32, o32, args.steps, args.warmup, profile=True)
     # the site correction alone on a potential from another solver (here the
     # tree's own, written by one evaluation)
     pot = torch.zeros(s.n_atoms, dtype=torch.float32, device=dev)
@@ -229,7 +230,7 @@ def main():
         qt[st.atoms] = st.lam @ st.charges
     mp = pkg.Mahi(s.box, True, qt, [], order=s.order, depth=s.depth, precision=32, stream=stream)
     op = outputs(torch.float32, 0)
-    tplain, _ = time_evals(mp, x32, op, args.steps, args.warmup)
+    tplain, _, _ = time_evals(mp, x32, op, args.steps, args.warmup)
     mp.close()
     print(f"[bench] fp32 plain FMM {tplain * 1e3:.3f} ms/eval", file=sys.stderr, flush=True)
 
@@ -237,7 +238,7 @@ def main():
     m64 = pkg.from_system(s, precision=64, stream=stream)
     x64 = torch.from_numpy(s.x.astype(np.float64)).to(dev)
     o64 = outputs(torch.float64, s.n_forms)
-    t64, _ = time_evals(m64, x64, o64, max(3, args.steps // 4), 1)
+    t64, _, _ = time_evals(m64, x64, o64, max(3, args.steps // 4), 1)
     m64.close()
     print(f"[bench] fp64 MAHI {t64 * 1e3:.3f} ms/eval", file=sys.stderr, flush=True)
 
@@ -251,6 +252,8 @@ def main():
     pairs = p2p_pairs(s, s.depth)
     extra = {
         "stage_ms": {k: round(v, 4) for k, v in stages.items()},
+        # device time of each timed evaluation (first to last stage event on the library's stream)
+        "eval_ns_p10_p50_p90": [float(np.percentile(per_eval, q)) * 1e6 for q in (10, 50, 90)],
         "fp64_ns_per_eval": t64 * 1e9,
         "fp32_speedup_over_fp64": t64 / t32,
         "plain_fmm_ns_per_eval": tplain * 1e9,

@@ -255,6 +255,11 @@ mahi_status mahi_device_selftest(int precision, double *max_rel_err);
 mahi_status mahi_profile_begin(mahi_ctx *ctx, int max_evals);
 mahi_status mahi_profile_end(mahi_ctx *ctx, double *stage_ms, int *n_evals);
 const char *mahi_stage_name(int stage);
+/* Per-evaluation durations (ms, first to last stage boundary on the context's
+ * stream) of the evaluations recorded by the last mahi_profile_begin /
+ * mahi_profile_end pair, in order: min(max, recorded) values are written to
+ * eval_ms and their number to *n.  MAHI_ESTATE before any profile has ended. */
+mahi_status mahi_profile_eval_times(const mahi_ctx *ctx, double *eval_ms, int max, int *n);
 
 /* Test hook: copy an internal buffer of the last evaluation to host memory.
  * which: 0 multipoles (all levels, level 0 first, boxes in Morton order,

@@ -72,6 +72,8 @@ struct mahi_ctx {
   static constexpr int kSlots = MAHI_N_STAGES + 3;
   std::vector<hipEvent_t> prof_events;
   int prof_max = 0, prof_n = 0;
+  std::vector<double> prof_totals;  // per-evaluation durations of the last ended profile
+  bool prof_done = false;
   void mark(int boundary) {
     if (prof_n < prof_max) (void)hipEventRecord(prof_events[(size_t)prof_n * kSlots + boundary], stream);
   }
@@ -804,12 +806,29 @@ mahi_status mahi_profile_end(mahi_ctx *ctx, double *stage_ms, int *n_evals) {
       HIP_TRY(hipEventElapsedTime(&ms, ctx->prof_events[a0], ctx->prof_events[a0 + 1]), "event timing");
       stage_ms[s] += ms;
     }
+  ctx->prof_totals.assign(ctx->prof_n, 0.0);
+  for (int e = 0; e < ctx->prof_n; ++e) {
+    const size_t base = (size_t)e * mahi_ctx::kSlots;
+    float ms = 0.f;
+    HIP_TRY(hipEventElapsedTime(&ms, ctx->prof_events[base], ctx->prof_events[base + MAHI_N_STAGES]), "event timing");
+    ctx->prof_totals[e] = ms;
+  }
+  ctx->prof_done = true;
   if (ctx->prof_n > 0)
     for (int s = 0; s < MAHI_N_STAGES; ++s) stage_ms[s] /= ctx->prof_n;
   if (n_evals) *n_evals = ctx->prof_n;
   for (auto &e : ctx->prof_events) (void)hipEventDestroy(e);
   ctx->prof_events.clear();
   ctx->prof_max = ctx->prof_n = 0;
+  return MAHI_OK;
+}
+
+mahi_status mahi_profile_eval_times(const mahi_ctx *ctx, double *eval_ms, int max, int *n) {
+  if (!ctx || !n || max < 0 || (max > 0 && !eval_ms)) return MAHI_EINVAL;
+  if (!ctx->prof_done) return MAHI_ESTATE;
+  const int m = std::min<int>(max, (int)ctx->prof_totals.size());
+  for (int i = 0; i < m; ++i) eval_ms[i] = ctx->prof_totals[i];
+  *n = m;
   return MAHI_OK;
 }
 

@@ -100,6 +100,9 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.mahi_profile_end.restype = ctypes.c_int
     lib.mahi_stage_name.argtypes = [ctypes.c_int]
     lib.mahi_stage_name.restype = ctypes.c_char_p
+    lib.mahi_profile_eval_times.argtypes = [vp, ctypes.POINTER(ctypes.c_double), ctypes.c_int,
+                                            ctypes.POINTER(ctypes.c_int)]
+    lib.mahi_profile_eval_times.restype = ctypes.c_int
     lib.mahi_debug_copy.argtypes = [vp, ctypes.c_int, vp, ctypes.c_int64]
     lib.mahi_debug_copy.restype = ctypes.c_int
     lib.mahi_set_form_charges.argtypes = [vp, ctypes.POINTER(ctypes.c_double)]
@@ -303,6 +306,14 @@ class Mahi:
         n = ctypes.c_int()
         _check(self._lib.mahi_profile_end(self._h, ms, ctypes.byref(n)), self._h)
         return {self._lib.mahi_stage_name(i).decode(): ms[i] for i in range(N_STAGES)}, n.value
+
+    def profile_eval_times(self, max_evals: int = 100000) -> np.ndarray:
+        """Per-evaluation durations (ms) of the last ended profile."""
+        out = np.zeros(max_evals)
+        n = ctypes.c_int()
+        _check(self._lib.mahi_profile_eval_times(self._h, _ptr(out, ctypes.c_double), int(max_evals),
+                                                 ctypes.byref(n)), self._h)
+        return out[:n.value]
 
     def debug_copy(self, which: int, count: int):
         """Copy an internal buffer of the last evaluation (test hook; see mahi_debug_copy)."""

@@ -171,3 +171,9 @@ def test_batch_create_validates_without_device():
     assert lib.mahi_batch_create(ctypes.byref(h), arr, 2, 1, None) == -1
     assert lib.mahi_batch_eval(None, None) == -1
     lib.mahi_batch_destroy(None)
+
+
+def test_profile_eval_times_validates():
+    lib = mb.load()
+    n = ctypes.c_int()
+    assert lib.mahi_profile_eval_times(None, None, 0, ctypes.byref(n)) == -1
