@@ -56,6 +56,8 @@ struct mahi_ctx {
   double *LamT = nullptr, *qds = nullptr, *epart = nullptr, *dE_site = nullptr, *dvdl = nullptr, *E = nullptr;
   double *bbox = nullptr, *lam = nullptr, *fq = nullptr;
   double *dedq = nullptr, *dvdl_qi = nullptr, *E_qi = nullptr;  // host-I/O staging of the optional outputs
+  double *site_ws = nullptr;  // site-pass work arrays in global memory when they exceed local memory
+  int64_t site_ws_stride = 0;  // doubles per site
   int4 *lists = nullptr;
   Geom *geom = nullptr;
   int *key = nullptr, *count = nullptr, *start = nullptr, *tmp = nullptr, *perm = nullptr,
@@ -282,6 +284,10 @@ mahi_status setup_device(mahi_ctx *ctx, const std::vector<double> &q_env, const 
     HIP_TRY(ctx->alloc(ctx->dvdl, sizeof(double) * ctx->nforms), "alloc dvdl");
     HIP_TRY(ctx->alloc(ctx->dvdl_qi, sizeof(double) * ctx->nforms), "alloc dvdl");
     HIP_TRY(ctx->alloc(ctx->dedq, sizeof(double) * fq.size()), "alloc dE/dq");
+    if (!site_in_lds(p, ctx->maxa, ctx->maxf)) {
+      ctx->site_ws_stride = (int64_t)(site_lds_bytes(p, ctx->maxa, ctx->maxf, true) / sizeof(double));
+      HIP_TRY(ctx->alloc(ctx->site_ws, sizeof(double) * ctx->site_ws_stride * ctx->M), "alloc site workspace");
+    }
     HIP_TRY(ctx->alloc(ctx->dE_site, sizeof(double) * ctx->M), "alloc site energies");
     HIP_TRY(hipMemcpy(ctx->atom_off, atom_off.data(), sizeof(int) * atom_off.size(), hipMemcpyHostToDevice), "upload");
     HIP_TRY(hipMemcpy(ctx->form_off, form_off.data(), sizeof(int) * form_off.size(), hipMemcpyHostToDevice), "upload");
@@ -383,7 +389,8 @@ mahi_status eval_impl(mahi_ctx *ctx, const mahi_eval_args *a) {
   ctx->mark(7);
   if (ctx->M > 0) {
     SiteArgs s = site_args<T>(ctx);
-    const SiteIO<T> io{static_cast<const T *>(ctx->phi_sorted), nullptr, F, dvdl, ctx->dE_site, dedq, dvdl_qi};
+    const SiteIO<T> io{static_cast<const T *>(ctx->phi_sorted), nullptr, F, dvdl, ctx->dE_site, dedq, dvdl_qi,
+                       ctx->site_ws, ctx->site_ws_stride};
     launch_site<T>(s, xyz, ctx->slot_of, ctx->geom, ctx->LamT, io, st);
   }
   ctx->mark(8);
@@ -435,7 +442,7 @@ mahi_status correct_impl(mahi_ctx *ctx, const mahi_correct_args *a) {
   double *dedq = a->dedq ? (dev ? a->dedq : ctx->dedq) : nullptr;
   if (ctx->M > 0) {
     SiteArgs s = site_args<T>(ctx);
-    const SiteIO<T> io{nullptr, pot, F, dvdl, ctx->dE_site, dedq, nullptr};
+    const SiteIO<T> io{nullptr, pot, F, dvdl, ctx->dE_site, dedq, nullptr, ctx->site_ws, ctx->site_ws_stride};
     launch_site<T>(s, xyz, ctx->slot_of, ctx->geom, ctx->LamT, io, st);
   }
   launch_finalize(nullptr, 0, ctx->dE_site, ctx->M, ctx->ke, E, nullptr, st);
@@ -610,10 +617,6 @@ mahi_status mahi_create(mahi_ctx **out, const mahi_box *box, int64_t n_atoms, co
   ctx->maxa = maxa;
   ctx->maxf = maxf;
   ctx->lambda_set = (M == 0);
-  if (M > 0 && site_lds_bytes(ctx->p, maxa, maxf, false) + kSiteStaticLds > (size_t)std::min<size_t>(prop.sharedMemPerBlock, 65536)) {
-    delete ctx;
-    return bad(MAHI_ERANGE, "order too high for the site correction's local memory with these site sizes");
-  }
   if (opts->hip_stream) {
     ctx->stream = static_cast<hipStream_t>(opts->hip_stream);
   } else {

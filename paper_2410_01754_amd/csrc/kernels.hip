@@ -1150,14 +1150,17 @@ __global__ void k_charge_scale(const int *__restrict__ atom_off, const int *__re
 //   dE/dq^r_i = ke lt_r (V_i + U^r_i - Ut_i)
 //   dE_QI/dlt_r = ke sum_i q^r_i V_i     (charge interpolation: E_QI = ke/2 qt.Phi.qt)
 // ---------------------------------------------------------------------------
-template <class T, int PT>
+template <class T, int PT, bool WS>
 __global__ void __launch_bounds__(256) k_site(SiteArgs a, const T *__restrict__ xyz, const int *__restrict__ slot_of,
                                               const Geom *__restrict__ gp, const double *__restrict__ LamT,
                                               SiteIO<T> io) {
   T *__restrict__ F = io.F;
   constexpr int NT = 256;
-  extern __shared__ double sm[];
+  extern __shared__ double sm_lds[];
   const int s = blockIdx.x, tid = threadIdx.x;
+  // work arrays in local memory, or (WS) this site's region of the global workspace;
+  // a compile-time choice, so that the local-memory case keeps LDS instructions
+  double *sm = WS ? io.ws + (size_t)s * io.ws_stride : sm_lds;
   const int na = a.atom_off[s + 1] - a.atom_off[s], nf = a.form_off[s + 1] - a.form_off[s];
   const int K = a.K, p = PT > 0 ? PT : a.p;
   __shared__ double x[kMaxSiteAtoms][3], V[kMaxSiteAtoms], qt[kMaxSiteAtoms], ut[kMaxSiteAtoms], lam[kMaxSiteForms];
@@ -1657,18 +1660,32 @@ size_t site_lds_bytes(int p, int maxa, int maxf, bool with_d) {
   return sizeof(double) * (4 * (size_t)maxa * maxa + (size_t)maxa * K + (with_d ? 5 : 2) * (size_t)maxf * K);
 }
 
+bool site_in_lds(int p, int maxa, int maxf) {
+  return site_lds_bytes(p, maxa, maxf, false) + kSiteStaticLds <= 65536;
+}
+
 template <class T>
 void launch_site(const SiteArgs &s, const T *xyz, const int *slot_of, const Geom *g, const double *LamT,
                  const SiteIO<T> &io, hipStream_t st) {
   if (s.n_sites == 0) return;
   SiteArgs a = s;
-  // gradient coefficients in LDS when they fit next to the kernel's static arrays
-  a.dloc = site_lds_bytes(s.p, s.maxa, s.maxf, true) + kSiteStaticLds <= 65536 ? 1 : 0;
-  const size_t lds = site_lds_bytes(s.p, s.maxa, s.maxf, a.dloc != 0);
-  if (s.p == 8)
-    hipLaunchKernelGGL((k_site<T, 8>), dim3(s.n_sites), dim3(256), lds, st, a, xyz, slot_of, g, LamT, io);
+  size_t lds = 0;
+  if (io.ws) {
+    a.dloc = 1;  // the workspace always has room for the gradient coefficients
+  } else {
+    // gradient coefficients in LDS when they fit next to the kernel's static arrays
+    a.dloc = site_lds_bytes(s.p, s.maxa, s.maxf, true) + kSiteStaticLds <= 65536 ? 1 : 0;
+    lds = site_lds_bytes(s.p, s.maxa, s.maxf, a.dloc != 0);
+  }
+  const dim3 grid(s.n_sites), block(256);
+  if (s.p == 8 && io.ws)
+    hipLaunchKernelGGL((k_site<T, 8, true>), grid, block, lds, st, a, xyz, slot_of, g, LamT, io);
+  else if (s.p == 8)
+    hipLaunchKernelGGL((k_site<T, 8, false>), grid, block, lds, st, a, xyz, slot_of, g, LamT, io);
+  else if (io.ws)
+    hipLaunchKernelGGL((k_site<T, 0, true>), grid, block, lds, st, a, xyz, slot_of, g, LamT, io);
   else
-    hipLaunchKernelGGL((k_site<T, 0>), dim3(s.n_sites), dim3(256), lds, st, a, xyz, slot_of, g, LamT, io);
+    hipLaunchKernelGGL((k_site<T, 0, false>), grid, block, lds, st, a, xyz, slot_of, g, LamT, io);
 }
 
 void launch_finalize(const double *epart, int nb, const double *dE_site, int ns, double ke, double *E, double *E_qi,

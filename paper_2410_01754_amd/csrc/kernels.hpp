@@ -60,6 +60,9 @@ struct SiteIO {
   double *dE_site;  // [M] intra-site correction energy (without ke)
   double *dedq;     // [sum forms * atoms] dE/dq^(s,r)_i, layout of the form charges
   double *dvdl_qi;  // [sum forms] ke sum_i q^r_i V_i (charge-interpolated derivative)
+  double *ws;       // per-site work arrays in global memory when they exceed local memory
+                    // (site s at ws + s * ws_stride doubles), else null
+  int64_t ws_stride;
 };
 
 template <class T>
@@ -104,5 +107,8 @@ void launch_site(const SiteArgs &s, const T *xyz, const int *slot_of, const Geom
 void launch_finalize(const double *epart, int nb, const double *dE_site, int ns, double ke, double *E, double *E_qi,
                      hipStream_t st);
 size_t site_lds_bytes(int p, int maxa, int maxf, bool with_d);
+// whether the site pass keeps its work arrays in local memory (else a global workspace
+// of site_lds_bytes(p, maxa, maxf, true) per site)
+bool site_in_lds(int p, int maxa, int maxf);
 
 }  // namespace mahi
