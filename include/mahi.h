@@ -130,8 +130,8 @@ mahi_status mahi_create(mahi_ctx **out, const mahi_box *box, int64_t n_atoms, co
 mahi_status mahi_set_lambda(mahi_ctx *ctx, const double *lambda_tilde);
 
 /* One evaluation: octree build, P2M, M2M, periodic lattice, M2L, L2L, L2P and
- * P2P on the scaled charges (the work of the upper tree levels on a second
- * stream of the context, beside the M2L of the two deepest levels),
+ * P2P on the scaled charges (the work of the upper tree levels, M2M included,
+ * on a second stream of the context, beside the M2L of the two deepest levels),
  * then the per-site correction (paper, section "Multipole-Accelerated
  * Hamiltonian Interpolation": eqs correction_scheme to C_B and the execution
  * order of section "Execution of MAHI").
@@ -245,12 +245,13 @@ mahi_status mahi_device_selftest(int precision, double *max_rel_err);
  * evaluations (no extra synchronisation).  mahi_profile_end waits for the
  * stream and writes the mean duration in ms of each stage over the recorded
  * evaluations to stage_ms[MAHI_N_STAGES] and their number to *n_evals.
- * Stages: 0 octree build, 1 P2M, 2 M2M, 3 upper levels, 4 M2L of the two
- * deepest levels, 5 L2L into the two deepest levels (after joining stage 3),
- * 6 P2P + L2P + outputs, 7 site correction, 8 energy reduction.  Stage 3 (M2L
- * of the upper levels, the periodic lattice and L2L into the upper levels)
- * runs on a second stream of the context concurrently with stage 4, so the
- * stages add up to more than the evaluation.                                */
+ * Stages: 0 octree build, 1 P2M, 2 M2M into level d-1, 3 upper levels, 4 M2L
+ * of the two deepest levels, 5 L2L into the two deepest levels (after joining
+ * stage 3), 6 P2P + L2P + outputs, 7 site correction, 8 energy reduction.
+ * Stage 3 (M2M into levels d-2..0, M2L of the upper levels, the periodic
+ * lattice and L2L into the upper levels) runs on a second stream of the
+ * context concurrently with stage 4, so the stages add up to more than the
+ * evaluation.                                                               */
 #define MAHI_N_STAGES 9
 mahi_status mahi_profile_begin(mahi_ctx *ctx, int max_evals);
 mahi_status mahi_profile_end(mahi_ctx *ctx, double *stage_ms, int *n_evals);

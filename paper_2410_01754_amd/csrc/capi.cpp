@@ -193,8 +193,8 @@ mahi_status setup_device(mahi_ctx *ctx, const std::vector<double> &q_env, const 
   HIP_TRY(ctx->alloc(ctx->Lc, sizeof(T) * (nbox + 1) * KS), "alloc locals");
   HIP_TRY(hipMemset(ctx->Mc, 0, sizeof(T) * (nbox + 1) * KS), "zero multipoles");
   HIP_TRY(hipMemset(ctx->Lc, 0, sizeof(T) * (nbox + 1) * KS), "zero locals");
-  if (f32 && ctx->plan32.nsplit > 1)
-    HIP_TRY(ctx->alloc(ctx->part, sizeof(T) * ctx->plan32.nsplit * nbox * KS), "alloc M2L partials");
+  const int nsplit_max = f32 ? std::max(ctx->plan32.nsplit, ctx->plan32.nsplit_up) : 1;
+  if (nsplit_max > 1) HIP_TRY(ctx->alloc(ctx->part, sizeof(T) * nsplit_max * nbox * KS), "alloc M2L partials");
   HIP_TRY(ctx->alloc(ctx->key, sizeof(int) * N), "alloc keys");
   HIP_TRY(ctx->alloc(ctx->tmp, sizeof(int) * N), "alloc scatter");
   HIP_TRY(ctx->alloc(ctx->perm, sizeof(int) * N), "alloc perm");
@@ -349,12 +349,13 @@ mahi_status eval_impl(mahi_ctx *ctx, const mahi_eval_args *a) {
   launch_p2m<T>(tb.sorted, ctx->start, nleaf, p, KS, Mc + level_offset(d) * KS, ctx->periodic ? ctx->qds : nullptr,
                 ctx->geom, d, st);
   ctx->mark(2);
-  // Levels hl..d (hl = max(lmin, d - 1)) carry almost all M2L work.  After the
-  // whole upward pass the side stream takes M2L of levels lmin..hl-1 (issued
-  // first, so its blocks are dispatched beside the main launch), the periodic
-  // lattice and L2L into levels up to hl - 1, while the main stream runs M2L of
-  // levels hl..d.  The two write disjoint level ranges; the main stream joins
-  // before L2L into levels hl..d.
+  // Levels hl..d (hl = max(lmin, d - 1)) carry almost all M2L work, and need
+  // multipoles of levels d - 1 and d only.  After the M2M into level d - 1 the
+  // side stream takes the M2M into levels d - 2..0, M2L of levels lmin..hl-1
+  // (issued before the main launch, so its blocks are dispatched beside it),
+  // the periodic lattice and L2L into levels up to hl - 1, while the main
+  // stream runs M2L of levels hl..d.  The two write disjoint level ranges; the
+  // main stream joins before L2L into levels hl..d.
   const int lmin = ctx->periodic ? 1 : 2;
   const int mlow = ctx->periodic ? 0 : 2;
   const int l2l_first = ctx->periodic ? 1 : 3;
@@ -368,11 +369,14 @@ mahi_status eval_impl(mahi_ctx *ctx, const mahi_eval_args *a) {
     else
       launch_xlate_m2l<T>(Mc, Lc, static_cast<const T *>(ctx->m2l), ctx->lists, p, KS, d, ctx->periodic, lo, hi, s);
   };
-  for (int l = d - 1; l >= mlow; --l) launch_updown<T>(Mc, Tm2m, p, KS, l, true, st);
+  // only the deepest M2M (parent level d - 1) precedes the fork: the main M2L
+  // needs multipoles of levels d - 1 and d only
+  if (d - 1 >= mlow) launch_updown<T>(Mc, Tm2m, p, KS, d - 1, true, st);
   ctx->mark(3);
   HIP_TRY(hipEventRecord(ctx->ev_fork, st), "fork");
   HIP_TRY(hipStreamWaitEvent(ctx->side, ctx->ev_fork, 0), "fork");
   ctx->mark_side(0);
+  for (int l = d - 2; l >= mlow; --l) launch_updown<T>(Mc, Tm2m, p, KS, l, true, ctx->side);
   m2l(lmin, hl - 1, ctx->side);
   if (ctx->periodic) launch_lattice<T>(Mc, Lc, ctx->LamT, ncoef(p), ctx->qds, nleaf, ctx->geom, ctx->side);
   for (int l = l2l_first; l <= std::min(hl - 1, d); ++l) launch_updown<T>(Lc, Tl2l, p, KS, l - 1, false, ctx->side);

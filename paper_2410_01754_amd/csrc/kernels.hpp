@@ -15,6 +15,7 @@ constexpr int kM2LMaxSplit = 8;
 
 struct M2LPlan {
   int K, KS, ns, nkc, ngroups, nsplit, ntiles;
+  int nsplit_up;  // operator ranges of launches that end below level d - 1 (few tiles each)
   int tile0, tile_run;  // tiles of one launch (a level range)
   int d, lmin, periodic;
   int64_t nbox, zbox;  // boxes over all levels; index of the all-zero multipole row

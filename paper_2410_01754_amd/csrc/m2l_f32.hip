@@ -448,6 +448,10 @@ void m2l32_plan(int p, int d, int periodic, int n_cu, M2LPlan &a) {
       }
     }
   }
+  // the upper levels hold a few tiles and run on a second stream beside the
+  // main launch: their blocks are chains of operator steps, shortest with the
+  // most ranges (measured: with 4 or 6 ranges that stream outlasts the main one)
+  a.nsplit_up = kM2LMaxSplit;
 }
 
 void launch_m2l_f32(const float *M, float *L, float *part, const float *Tab, const int4 *lists, const M2LPlan &plan,
@@ -456,6 +460,7 @@ void launch_m2l_f32(const float *M, float *L, float *part, const float *Tab, con
   lev_hi = std::min(lev_hi, plan.d);
   if (plan.ntiles == 0 || lev_lo > lev_hi) return;
   M2LPlan a = plan;
+  if (lev_hi < plan.d - 1) a.nsplit = plan.nsplit_up;
   a.tile0 = plan.tiles_start[lev_lo];
   a.tile_run = plan.tiles_start[lev_hi + 1] - a.tile0;  // a multiple of 8 (8 classes per chunk)
   if (a.tile_run <= 0) return;
