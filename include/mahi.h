@@ -235,9 +235,11 @@ mahi_status mahi_info(const mahi_ctx *ctx, int64_t *n_atoms, int32_t *n_sites, i
  * largest relative deviation found to *max_rel_err.                         */
 mahi_status mahi_host_selftest(int order, double *max_rel_err);
 
-/* Device check of the matrix-core tile layout used by the M2L contraction:
- * multiplies random matrices with the kernel's tile code and compares with a
- * host product.  precision 32 or 64.  Writes the largest relative error.     */
+/* Device check of the matrix-core tile layouts used by the translation
+ * kernels: multiplies random matrices with each kernel's tile code (float32:
+ * the 32x32x2 tile and the 16x16x4 tile of the M2L kernel for orders up to 8;
+ * float64: the 16x16x4 tile) and compares with a host product.  precision 32
+ * or 64.  Writes the largest relative error.                               */
 mahi_status mahi_device_selftest(int precision, double *max_rel_err);
 
 /* Stage timing.  Between mahi_profile_begin and mahi_profile_end the library

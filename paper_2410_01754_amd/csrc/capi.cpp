@@ -1052,7 +1052,9 @@ mahi_status mahi_device_selftest(int precision, double *max_rel_err) {
   for (int r = 0; r < rows; ++r)
     for (int c = 0; c < 64; ++c)
       for (int k = 0; k < kk; ++k) C[(size_t)r * 64 + c] += A[(size_t)k * rows + r] * B[(size_t)k * 64 + c];
-  auto run = [&](auto zero) -> mahi_status {
+  // probe: 0 the tile code of the generic translation kernels (32x32x2 float32,
+  // 16x16x4 float64), 1 the float32 16x16x4 tile of the M2L kernel for orders up to 8
+  auto run = [&](auto zero, int probe) -> mahi_status {
     using T = decltype(zero);
     std::vector<T> a(A.begin(), A.end()), b(B.begin(), B.end()), c((size_t)rows * 64);
     T *da = nullptr, *db = nullptr, *dc = nullptr;
@@ -1061,7 +1063,12 @@ mahi_status mahi_device_selftest(int precision, double *max_rel_err) {
       return MAHI_ENOMEM;
     (void)hipMemcpy(da, a.data(), sizeof(T) * a.size(), hipMemcpyHostToDevice);
     (void)hipMemcpy(db, b.data(), sizeof(T) * b.size(), hipMemcpyHostToDevice);
-    launch_mfma_probe<T>(da, db, dc, rows, kk, nullptr);
+    if constexpr (sizeof(T) == sizeof(float)) {
+      if (probe == 1) launch_mfma16_probe(da, db, dc, rows, kk, nullptr);
+      else launch_mfma_probe<T>(da, db, dc, rows, kk, nullptr);
+    } else {
+      launch_mfma_probe<T>(da, db, dc, rows, kk, nullptr);
+    }
     hipError_t e = hipDeviceSynchronize();
     (void)hipMemcpy(c.data(), dc, sizeof(T) * c.size(), hipMemcpyDeviceToHost);
     (void)hipFree(da);
@@ -1073,10 +1080,13 @@ mahi_status mahi_device_selftest(int precision, double *max_rel_err) {
       worst = std::max(worst, std::fabs((double)c[i] - C[i]));
       nrm = std::max(nrm, std::fabs(C[i]));
     }
-    *max_rel_err = worst / nrm;
+    *max_rel_err = std::max(*max_rel_err, worst / nrm);
     return MAHI_OK;
   };
-  return precision == 32 ? run(0.0f) : run(0.0);
+  *max_rel_err = 0.0;
+  if (precision == 64) return run(0.0, 0);
+  const mahi_status st = run(0.0f, 0);
+  return st != MAHI_OK ? st : run(0.0f, 1);
 }
 
 }  // extern "C"

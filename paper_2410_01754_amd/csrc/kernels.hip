@@ -566,6 +566,21 @@ struct Mfma<double> {
   __device__ static int d_col(int l, int) { return l & 15; }
 };
 
+// float32 16x16x4 tile as used by the M2L kernel for orders up to 8: lane l
+// supplies A row l % 16 and B column l % 16 of k group l / 16, and holds output
+// rows 4 (l / 16) .. + 3 of column l % 16
+struct Mfma16f32 {
+  static constexpr int TM = 16, TN = 16, TK = 4, NACC = 4;
+  typedef float acc_t __attribute__((ext_vector_type(4)));
+  __device__ static acc_t mma(float a, float b, acc_t c) { return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0); }
+  __device__ static int a_row(int l) { return l & 15; }
+  __device__ static int a_k(int l) { return l >> 4; }
+  __device__ static int b_k(int l) { return l >> 4; }
+  __device__ static int b_col(int l) { return l & 15; }
+  __device__ static int d_row(int l, int r) { return 4 * (l >> 4) + r; }
+  __device__ static int d_col(int l, int) { return l & 15; }
+};
+
 constexpr int kBStride = 65;  // LDS row stride of the staged B operand (64 targets + 1 pad)
 
 // ---------------------------------------------------------------------------
@@ -814,9 +829,8 @@ __global__ void __launch_bounds__(1024) k_updown(T *__restrict__ X, const T *__r
 
 // Matrix-core tile check: C[rows x 64] = A[rows x kk] * B[kk x 64] with the same
 // fragment mapping as k_xlate (A given k-major as [kk][rows]).
-template <class T>
+template <class T, class MF = Mfma<T>>
 __global__ void k_mfma_probe(const T *__restrict__ A, const T *__restrict__ B, T *__restrict__ C, int rows, int kk) {
-  using MF = Mfma<T>;
   constexpr int NCT = 64 / MF::TN;
   const int lane = threadIdx.x & 63;
   const int rt = threadIdx.x >> 6;
@@ -1617,6 +1631,11 @@ template <class T>
 void launch_mfma_probe(const T *A, const T *B, T *C, int rows, int kk, hipStream_t st) {
   using MF = Mfma<T>;
   hipLaunchKernelGGL(k_mfma_probe<T>, dim3(1), dim3(64 * (rows / MF::TM)), 0, st, A, B, C, rows, kk);
+}
+
+void launch_mfma16_probe(const float *A, const float *B, float *C, int rows, int kk, hipStream_t st) {
+  hipLaunchKernelGGL((k_mfma_probe<float, Mfma16f32>), dim3(1), dim3(64 * (rows / Mfma16f32::TM)), 0, st, A, B, C,
+                     rows, kk);
 }
 
 template <class T>

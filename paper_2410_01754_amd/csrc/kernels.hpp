@@ -97,6 +97,8 @@ template <class T> void updown_table(int K, int KS, const double *const *Tc, T *
 template <class T> size_t updown_lds(int KS, bool up);
 template <class T> void launch_updown(T *X, const T *A, int p, int KS, int parent_level, bool up, hipStream_t st);
 template <class T> void launch_mfma_probe(const T *A, const T *B, T *C, int rows, int kk, hipStream_t st);
+// the same check for the float32 16x16x4 tile of the M2L kernel for orders up to 8
+void launch_mfma16_probe(const float *A, const float *B, float *C, int rows, int kk, hipStream_t st);
 template <class T> int p2p_blocks(int d);
 template <class T>
 void launch_p2p(const Atom4<T> *sorted, const int *start, const int *perm, const T *Lleaf, int KS, const Geom *g, int d,
