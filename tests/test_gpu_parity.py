@@ -206,3 +206,16 @@ def test_config2_full_size_sampled():
     ee = abs(g["energy"] - gd["energy"][0]) / abs(gd["energy"][0])
     print(f"config2 fp32 p=8: E {ee:.3e} F {ef:.3e} dVdl {ed:.3e}")
     assert ef <= 2e-4 and ed <= 2e-4 and ee <= 2e-4
+
+
+def test_config2_full_size_float64():
+    """The float64 path at paper scale (the one the float32 speedup is measured
+    against), order 8, depth 5: the same order-8 truncation bound."""
+    gd = _golden(2)
+    s = make_config(2)
+    g = gpu_eval(s, 64, 8, 5)
+    idx = gd["idx"]
+    ef, ed = rel(g["forces"][idx], gd["forces"]), rel(g["dvdl"], gd["dvdl"])
+    ee = abs(g["energy"] - gd["energy"][0]) / abs(gd["energy"][0])
+    print(f"config2 fp64 p=8: E {ee:.3e} F {ef:.3e} dVdl {ed:.3e}")
+    assert ef <= 2e-4 and ed <= 2e-4 and ee <= 2e-4
