@@ -153,11 +153,12 @@ def cpu_baseline(full_n: int):
     from oracle import hi
     from synth import make_system
     cores = os.cpu_count() or 1
-    pts = []
+    pts, small = [], None
     for edge in (6.0, 8.5, 11.0):
         nw = int(round(33.4 * edge ** 3))
         ns = max(1, int(round(3 * nw / 1960)))
         s = make_system(nw, edge, True, [8] * ns, [2] * ns, total_step=1.0, depth=3, seed=7)
+        small = small if pts else s
         t0 = time.perf_counter()
         hi.hi_periodic(s.x, s.q, s.sites, s.box)
         pts.append((s.n_atoms, time.perf_counter() - t0))
@@ -166,9 +167,17 @@ def cpu_baseline(full_n: int):
     expo, icpt = np.polyfit(ln, lt, 1)
     t_full = float(np.exp(icpt + expo * np.log(full_n)))
     desc = ", ".join(f"{n} atoms {t:.2f}s" for n, t in pts)
+    # one thread on the smallest cube, scaled with the same exponent
+    s = small
+    t0 = time.perf_counter()
+    hi.hi_periodic(s.x, s.q, s.sites, s.box, nthreads=1)
+    t1 = time.perf_counter() - t0
+    t1_full = float(t1 * (full_n / s.n_atoms) ** expo)
     return {"value": t_full * 1e9, "unit": "ns/eval", "cores": cores, "kind": "oracle",
             "sample": f"full HI evaluation of 6.0, 8.5 and 11.0 nm cubes of the same recipe ({desc}); "
-                      f"scaled to {full_n} atoms with the fitted exponent {expo:.2f}"}
+                      f"scaled to {full_n} atoms with the fitted exponent {expo:.2f}",
+            "single_core_value": t1_full * 1e9,
+            "single_core_sample": f"the 6.0 nm cube on one thread ({s.n_atoms} atoms {t1:.2f}s), same exponent"}
 
 
 def main():
