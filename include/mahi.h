@@ -250,10 +250,10 @@ mahi_status mahi_device_selftest(int precision, double *max_rel_err);
  * Stages: 0 octree build, 1 P2M, 2 M2M into level d-1, 3 upper levels, 4 M2L
  * of the two deepest levels, 5 L2L into the two deepest levels (after joining
  * stage 3), 6 P2P + L2P + outputs, 7 site correction, 8 energy reduction.
- * Stage 3 (M2M into levels d-2..0, M2L of the upper levels, the periodic
- * lattice and L2L into the upper levels) runs on a second stream of the
- * context concurrently with stage 4, so the stages add up to more than the
- * evaluation.                                                               */
+ * Stage 3 (lattice charge moments, M2M into levels d-2..0, M2L of the upper
+ * levels, the periodic lattice and L2L into the upper levels) runs on a
+ * second stream of the context concurrently with stage 4, so the stages add
+ * up to more than the evaluation.                                           */
 #define MAHI_N_STAGES 9
 mahi_status mahi_profile_begin(mahi_ctx *ctx, int max_evals);
 mahi_status mahi_profile_end(mahi_ctx *ctx, double *stage_ms, int *n_evals);

@@ -202,7 +202,7 @@ mahi_status setup_device(mahi_ctx *ctx, const std::vector<double> &q_env, const 
   HIP_TRY(ctx->alloc(ctx->count, sizeof(int) * nleaf), "alloc counts");
   HIP_TRY(hipMemset(ctx->count, 0, sizeof(int) * nleaf), "zero counts");  // k_scan clears them after each use
   HIP_TRY(ctx->alloc(ctx->start, sizeof(int) * (nleaf + 1)), "alloc starts");
-  HIP_TRY(ctx->alloc(ctx->qds, sizeof(double) * 5 * nleaf), "alloc moments");
+  HIP_TRY(ctx->alloc(ctx->qds, sizeof(double) * 5 * (nleaf + kMomentBlocks)), "alloc moments");  // + block partials
   HIP_TRY(ctx->alloc(ctx->epart, sizeof(double) * p2p_blocks<T>(d)), "alloc energy partials");
   HIP_TRY(ctx->alloc(ctx->E, sizeof(double) * 1), "alloc energy");
   HIP_TRY(ctx->alloc(ctx->E_qi, sizeof(double) * 1), "alloc energy");
@@ -351,9 +351,10 @@ mahi_status eval_impl(mahi_ctx *ctx, const mahi_eval_args *a) {
   ctx->mark(2);
   // Levels hl..d (hl = max(lmin, d - 1)) carry almost all M2L work, and need
   // multipoles of levels d - 1 and d only.  After the M2M into level d - 1 the
-  // side stream takes the M2M into levels d - 2..0, M2L of levels lmin..hl-1
-  // (issued before the main launch, so its blocks are dispatched beside it),
-  // the periodic lattice and L2L into levels up to hl - 1, while the main
+  // side stream takes the lattice charge moments, the M2M into levels
+  // d - 2..0, M2L of levels lmin..hl-1 (issued before the main launch, so its
+  // blocks are dispatched beside it), the periodic lattice and L2L into
+  // levels up to hl - 1, while the main
   // stream runs M2L of levels hl..d.  The two write disjoint level ranges; the
   // main stream joins before L2L into levels hl..d.
   const int lmin = ctx->periodic ? 1 : 2;
@@ -376,9 +377,10 @@ mahi_status eval_impl(mahi_ctx *ctx, const mahi_eval_args *a) {
   HIP_TRY(hipEventRecord(ctx->ev_fork, st), "fork");
   HIP_TRY(hipStreamWaitEvent(ctx->side, ctx->ev_fork, 0), "fork");
   ctx->mark_side(0);
+  if (ctx->periodic) launch_moments(ctx->qds, nleaf, ctx->qds + 5 * (int64_t)nleaf, ctx->side);
   for (int l = d - 2; l >= mlow; --l) launch_updown<T>(Mc, Tm2m, p, KS, l, true, ctx->side);
   m2l(lmin, hl - 1, ctx->side);
-  if (ctx->periodic) launch_lattice<T>(Mc, Lc, ctx->LamT, ncoef(p), ctx->qds, nleaf, ctx->geom, ctx->side);
+  if (ctx->periodic) launch_lattice<T>(Mc, Lc, ctx->LamT, ncoef(p), ctx->qds + 5 * (int64_t)nleaf, ctx->geom, ctx->side);
   for (int l = l2l_first; l <= std::min(hl - 1, d); ++l) launch_updown<T>(Lc, Tl2l, p, KS, l - 1, false, ctx->side);
   ctx->mark_side(1);
   HIP_TRY(hipEventRecord(ctx->ev_join, ctx->side), "join");

@@ -478,8 +478,31 @@ __global__ void __launch_bounds__(64) k_p2m(const Atom4<T> *__restrict__ sorted,
 }
 
 // ---------------------------------------------------------------------------
+// Charge moments Q, D, S2 of the lattice remainder, first stage: block b sums
+// the per-leaf moments of leaves b*256 + t, stepping over all blocks, then its
+// 256 partials in a fixed tree.  Small blocks, so that the kernel runs beside
+// the M2L launches instead of waiting for a free CU.
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) k_moments(const double *__restrict__ qds, int nleaf, double *__restrict__ part) {
+  __shared__ double red[5][256];
+  const int t = threadIdx.x;
+  double v[5] = {0, 0, 0, 0, 0};
+  for (int l = blockIdx.x * 256 + t; l < nleaf; l += kMomentBlocks * 256)
+    for (int k = 0; k < 5; ++k) v[k] += qds[(int64_t)l * 5 + k];
+  for (int k = 0; k < 5; ++k) red[k][t] = v[k];
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (t < w)
+      for (int k = 0; k < 5; ++k) red[k][t] += red[k][t + w];
+    __syncthreads();
+  }
+  if (t < 5) part[blockIdx.x * 5 + t] = red[t][0];
+}
+
+// ---------------------------------------------------------------------------
 // Periodic lattice: root local from the root multipole (float64), plus the
-// float64 charge moments Q, D, S2 of the r^2 part of the lattice remainder.
+// float64 charge moments Q, D, S2 of the r^2 part of the lattice remainder
+// (summed from nleaf rows of five moments: the block partials of k_moments).
 // ---------------------------------------------------------------------------
 template <class T>
 __global__ void __launch_bounds__(1024) k_lattice(const T *__restrict__ M, T *__restrict__ L,
@@ -1482,9 +1505,13 @@ void launch_p2m(const Atom4<T> *sorted, const int *start, int nleaf, int p, int 
                        Mleaf, qds, g, d);
 }
 
+void launch_moments(const double *qds, int nleaf, double *part, hipStream_t st) {
+  hipLaunchKernelGGL(k_moments, dim3(kMomentBlocks), dim3(256), 0, st, qds, nleaf, part);
+}
+
 template <class T>
-void launch_lattice(const T *M, T *L, const double *LamT, int K, const double *qds, int nleaf, Geom *g, hipStream_t st) {
-  hipLaunchKernelGGL(k_lattice<T>, dim3(1), dim3(1024), 0, st, M, L, LamT, K, qds, nleaf, g);
+void launch_lattice(const T *M, T *L, const double *LamT, int K, const double *part, Geom *g, hipStream_t st) {
+  hipLaunchKernelGGL(k_lattice<T>, dim3(1), dim3(1024), 0, st, M, L, LamT, K, part, kMomentBlocks, g);
 }
 
 // Operator tables: [slot][KK][RP], k padded with zero rows to whole chunks of
@@ -1718,7 +1745,7 @@ void launch_finalize(const double *epart, int nb, const double *dE_site, int ns,
   template void launch_tree<T>(const T *, const T *, int64_t, const Geom *, int, int, TreeBufs<T>, hipStream_t);     \
   template void launch_p2m<T>(const Atom4<T> *, const int *, int, int, int, T *, double *, const Geom *, int,         \
                               hipStream_t);                                                                         \
-  template void launch_lattice<T>(const T *, T *, const double *, int, const double *, int, Geom *, hipStream_t);    \
+  template void launch_lattice<T>(const T *, T *, const double *, int, const double *, Geom *, hipStream_t);            \
   template void m2l_table_layout<T>(int, int &, int &);                                                               \
   template void launch_mfma_probe<T>(const T *, const T *, T *, int, int, hipStream_t);                              \
   template void launch_xlate_m2l<T>(const T *, T *, const T *, const int4 *, int, int, int, int, int, int,            \

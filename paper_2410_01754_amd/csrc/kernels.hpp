@@ -81,7 +81,10 @@ template <class T>
 void launch_p2m(const Atom4<T> *sorted, const int *start, int nleaf, int p, int KS, T *Mleaf, double *qds, const Geom *g,
                 int d, hipStream_t st);
 template <class T>
-void launch_lattice(const T *M, T *L, const double *LamT, int K, const double *qds, int nleaf, Geom *g, hipStream_t st);
+void launch_lattice(const T *M, T *L, const double *LamT, int K, const double *part, Geom *g, hipStream_t st);
+// block partials of the lattice charge moments (kMomentBlocks rows of five)
+constexpr int kMomentBlocks = 64;
+void launch_moments(const double *qds, int nleaf, double *part, hipStream_t st);
 template <class T> void m2l_table_layout(int p, int &KK, int &RP);
 template <class T>
 void launch_xlate_m2l(const T *M, T *L, const T *Tab, const int4 *lists, int p, int KS, int d, int periodic, int lev_lo,
