@@ -270,7 +270,8 @@ __device__ __forceinline__ void locate(const T *xyz, int64_t i, const Geom &g, i
 
 // Leaf key of every atom, its arrival rank within the leaf (the order of
 // equal keys is fixed later by k_leafsort) and its packed leaf-local
-// coordinates (leaf units, centred) with the scaled charge.
+// coordinates (leaf units, centred) with the scaled charge.  Consecutive
+// atoms that fall in one leaf take their ranks with a single atomic.
 template <class T>
 __global__ void k_bin(const T *__restrict__ xyz, const T *__restrict__ qt, int64_t n_atoms,
                       const Geom *__restrict__ gp, int d, int periodic, int *__restrict__ key, int *__restrict__ rank,
@@ -278,19 +279,38 @@ __global__ void k_bin(const T *__restrict__ xyz, const T *__restrict__ qt, int64
   const Geom g = *gp;
   const int n = 1 << d;
   const double inv_h = n / g.edge;
-  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n_atoms; i += (int64_t)gridDim.x * blockDim.x) {
-    double w[3];
-    int c[3];
-    locate(xyz, i, g, periodic, n, w, c);
-    const int k = (int)morton(c[0], c[1], c[2]);
-    key[i] = k;
-    Atom4<T> at;
-    at.x = (T)(w[0] * inv_h - (c[0] + 0.5));
-    at.y = (T)(w[1] * inv_h - (c[1] + 0.5));
-    at.z = (T)(w[2] * inv_h - (c[2] + 0.5));
-    at.q = qt[i];
-    packed[i] = at;
-    rank[i] = atomicAdd(&count[k], 1);
+  const int lane = threadIdx.x & 63;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  // whole waves step together (the loop bound is the same for every lane)
+  for (int64_t i0 = blockIdx.x * (int64_t)blockDim.x + (threadIdx.x - lane); i0 < n_atoms; i0 += stride) {
+    const int64_t i = i0 + lane;
+    const bool valid = i < n_atoms;
+    int k = -1;
+    if (valid) {
+      double w[3];
+      int c[3];
+      locate(xyz, i, g, periodic, n, w, c);
+      k = (int)morton(c[0], c[1], c[2]);
+      key[i] = k;
+      Atom4<T> at;
+      at.x = (T)(w[0] * inv_h - (c[0] + 0.5));
+      at.y = (T)(w[1] * inv_h - (c[1] + 0.5));
+      at.z = (T)(w[2] * inv_h - (c[2] + 0.5));
+      at.q = qt[i];
+      packed[i] = at;
+    }
+    // a run of equal keys on consecutive lanes (the atoms of one molecule)
+    // reserves its ranks with one atomic by its first lane
+    const int prev = __shfl_up(k, 1, 64);
+    const bool head = lane == 0 || prev != k;
+    const unsigned long long heads = __ballot(head);
+    const int h = 63 - __builtin_clzll(heads & (~0ull >> (63 - lane)));
+    const unsigned long long above = h == 63 ? 0ull : heads & ~(~0ull >> (63 - h));
+    const int len = above ? __builtin_ctzll(above) - h : 64 - h;
+    int base = 0;
+    if (head && valid) base = atomicAdd(&count[k], len);
+    base = __shfl(base, h, 64);
+    if (valid) rank[i] = base + (lane - h);
   }
 }
 
