@@ -10,14 +10,16 @@ Reported next to the headline ns/eval:
   * the float64 GPU path on the same system (FP32 speedup),
   * the plain FMM on the same scaled charges with no sites (MAHI overhead %),
   * per-stage mean durations from HIP events recorded on the library's stream
-    over the timed region, and the roofline of the dominant kernel (M2L),
+    over the timed region, and the roofline of the dominant kernel (M2L) and
+    of the near field (P2P + L2P, bound by the vector ALU),
   * the site correction alone (mahi_correct) on a given potential,
   * a batch of 96 small systems (3k..60k atoms, autotuned order and depth):
     per-system latency and eager batched throughput (extra.batch96),
-  * the CPU oracle on a bounded sample (same recipe, smaller cube), scaled to
-    the full system by the oracle's measured size exponent.
+  * the CPU oracle on a bounded sample (same recipe, smaller cubes), scaled to
+    the full system by the oracle's reciprocal-space work (--cpu-full also
+    times it on the whole workload, which takes minutes).
 
-Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-batch]
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-batch] [--cpu-full]
 """
 from __future__ import annotations
 
@@ -36,6 +38,12 @@ sys.path.insert(0, ROOT)
 PEAK_FP32_MATRIX_TFLOPS = 157.3
 PEAK_FP64_MATRIX_TFLOPS = 78.6
 PEAK_FP32_VECTOR_TFLOPS = 157.3
+# float32 vector ALU without packed operations (which this build does not emit):
+# 256 CUs x 64 lanes x 2 flop (FMA) x 2.4 GHz
+PEAK_FP32_VECTOR_UNPACKED_TFLOPS = 78.6
+# near-field pair: 13 vector instructions + one quarter-rate reciprocal square
+# root = 17 lane-cycles; 256 CUs x 64 lanes x 2.4 GHz / 17
+P2P_PAIR_BOUND_PER_S = 256 * 64 * 2.4e9 / 17
 
 
 def m2l_translations(depth: int, periodic: bool, lowest: int = 0) -> int:
@@ -147,12 +155,39 @@ def batch_leg(steps: int):
             "depth_histogram": {str(d): depths.count(d) for d in sorted(set(depths))}}
 
 
-def cpu_baseline(full_n: int):
-    """Oracle (Ewald HI, float64, all host cores) on three smaller cubes of the same
-    recipe; the full-size time is extrapolated with the log-log fitted size exponent."""
+def oracle_kspace_work(n: int, edge: float) -> float:
+    """Phase evaluations e^{ik.x} of the oracle's reciprocal-space sums for n atoms
+    in a cube of this edge: the structure factor over all atoms plus the sum at
+    every atom, 2 n n_k, with the oracle's own splitting parameter and cutoffs."""
+    from oracle import ewald
+    a = ewald.default_alpha(n, edge)
+    _, mmax = ewald.cutoffs(a, edge)
+    m = np.arange(-mmax, mmax + 1)
+    m2 = m[:, None, None] ** 2 + m[None, :, None] ** 2 + m[None, None, :] ** 2
+    nk = int(((m2 <= mmax * mmax).sum() - 1) // 2)
+    return 2.0 * n * nk
+
+
+def oracle_threads() -> int:
+    """Threads the oracle runs on: the host's cores, capped by OMP_NUM_THREADS when set."""
+    t = os.cpu_count() or 1
+    try:
+        t = min(t, int(os.environ.get("OMP_NUM_THREADS", t)))
+    except ValueError:
+        pass
+    return max(1, t)
+
+
+def cpu_baseline(full_n: int, full_edge: float, full_system=None):
+    """The oracle (float64 Ewald HI, every thread of oracle_threads()) timed on
+    smaller cubes of the same recipe, scaled to the full system by its
+    reciprocal-space work (2 N n_k phase evaluations, the term that dominates
+    the oracle's cost: a fit with a real-space term gives it no weight), using
+    the time per unit of work of the largest sample.  With full_system the
+    oracle is also timed on the whole workload (minutes)."""
     from oracle import hi
     from synth import make_system
-    cores = os.cpu_count() or 1
+    th = oracle_threads()
     pts, small = [], None
     for edge in (6.0, 8.5, 11.0):
         nw = int(round(33.4 * edge ** 3))
@@ -160,24 +195,32 @@ def cpu_baseline(full_n: int):
         s = make_system(nw, edge, True, [8] * ns, [2] * ns, total_step=1.0, depth=3, seed=7)
         small = small if pts else s
         t0 = time.perf_counter()
-        hi.hi_periodic(s.x, s.q, s.sites, s.box)
-        pts.append((s.n_atoms, time.perf_counter() - t0))
-    ln = np.log([p[0] for p in pts])
-    lt = np.log([p[1] for p in pts])
-    expo, icpt = np.polyfit(ln, lt, 1)
-    t_full = float(np.exp(icpt + expo * np.log(full_n)))
-    desc = ", ".join(f"{n} atoms {t:.2f}s" for n, t in pts)
-    # one thread on the smallest cube, scaled with the same exponent
+        hi.hi_periodic(s.x, s.q, s.sites, s.box, nthreads=th)
+        pts.append((s.n_atoms, edge, time.perf_counter() - t0))
+    w_full = oracle_kspace_work(full_n, full_edge)
+    n_l, e_l, t_l = pts[-1]
+    t_full = t_l * w_full / oracle_kspace_work(n_l, e_l)
+    expo, icpt = np.polyfit(np.log([p[0] for p in pts]), np.log([p[2] for p in pts]), 1)
+    t_pow = float(np.exp(icpt + expo * np.log(full_n)))
+    desc = ", ".join(f"{e:g} nm {n} atoms {t:.2f} s" for n, e, t in pts)
     s = small
     t0 = time.perf_counter()
     hi.hi_periodic(s.x, s.q, s.sites, s.box, nthreads=1)
     t1 = time.perf_counter() - t0
-    t1_full = float(t1 * (full_n / s.n_atoms) ** expo)
-    return {"value": t_full * 1e9, "unit": "ns/eval", "cores": cores, "kind": "oracle",
-            "sample": f"full HI evaluation of 6.0, 8.5 and 11.0 nm cubes of the same recipe ({desc}); "
-                      f"scaled to {full_n} atoms with the fitted exponent {expo:.2f}",
-            "single_core_value": t1_full * 1e9,
-            "single_core_sample": f"the 6.0 nm cube on one thread ({s.n_atoms} atoms {t1:.2f}s), same exponent"}
+    t1_full = t1 * w_full / oracle_kspace_work(s.n_atoms, s.box)
+    out = {"value": t_full * 1e9, "unit": "ns/eval", "cores": th, "kind": "oracle",
+           "sample": f"full HI evaluation of 6, 8.5 and 11 nm cubes of the same recipe on {th} threads ({desc}); "
+                     f"scaled to {full_n} atoms by the oracle's reciprocal-space work (2 N n_k phase "
+                     f"evaluations: {w_full:.3e} against {oracle_kspace_work(n_l, e_l):.3e} for the 11 nm cube)",
+           "power_law_value": t_pow * 1e9, "power_law_exponent": float(expo),
+           "single_core_value": t1_full * 1e9,
+           "single_core_sample": f"the 6 nm cube on one thread ({s.n_atoms} atoms {t1:.2f} s), same work scaling"}
+    if full_system is not None:
+        s = full_system
+        t0 = time.perf_counter()
+        hi.hi_periodic(s.x, s.q, s.sites, s.box, nthreads=th)
+        out["measured_full_value"] = (time.perf_counter() - t0) * 1e9
+    return out
 
 
 def main():
@@ -188,6 +231,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--config", type=int, default=2)
+    ap.add_argument("--cpu-full", action="store_true", help="also time the oracle on the whole workload (minutes)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: the hot path runs on one MI355X (no multi-GPU path).",
@@ -259,6 +303,7 @@ def main():
     m2l_s = stages["m2l"] * 1e-3
     achieved = m2l_flop / m2l_s / 1e12
     pairs = p2p_pairs(s, s.depth)
+    p2p_tflops = 20.0 * pairs / (stages["p2p_l2p"] * 1e-3) / 1e12
     extra = {
         "stage_ms": {k: round(v, 4) for k, v in stages.items()},
         # device time of each timed evaluation (first to last stage event on the library's stream)
@@ -292,13 +337,17 @@ def main():
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": PEAK_FP32_MATRIX_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / PEAK_FP32_MATRIX_TFLOPS, "traffic": m2l_traffic(),
                      "kernel": "m2l", "flop_per_launch": m2l_flop},
+        "roofline_p2p": {"bound": "alu", "achieved": p2p_tflops, "peak": PEAK_FP32_VECTOR_UNPACKED_TFLOPS,
+                         "unit": "TFLOP/s", "frac": p2p_tflops / PEAK_FP32_VECTOR_UNPACKED_TFLOPS,
+                         "traffic": None, "kernel": "p2p_l2p", "flop_per_launch": 20.0 * pairs,
+                         "frac_of_pair_instruction_bound": pairs / P2P_PAIR_BOUND_PER_S / (stages["p2p_l2p"] * 1e-3)},
         "extra": extra,
     }
     if not args.no_batch:
         extra["batch96"] = batch_leg(max(3, args.steps // 4))
         print(f"[bench] batch {extra['batch96']}", file=sys.stderr, flush=True)
     if not args.no_cpu:
-        line["cpu_baseline"] = cpu_baseline(s.n_atoms)
+        line["cpu_baseline"] = cpu_baseline(s.n_atoms, s.box, s if args.cpu_full else None)
     print(json.dumps(line))
 
 

@@ -116,17 +116,26 @@ typedef struct {
   double *dvdl_qi;    /* [sum forms] dE_QI/dlambda-tilde = coulomb_k sum_{i in s} q^(s,r)_i V_i */
 } mahi_eval_args;
 
-/* Create a context: validates everything, chooses no parameters on its own,
- * generates the translation and lattice tables in float64 on the host, and
- * allocates all device buffers.  charges[N] are the environment charges;
- * entries at site atoms are ignored.  sites may be NULL (plain FMM).       */
+/* Create a context for N point charges in a cube (periodic: eq nbody_periodic;
+ * open: the plain Coulomb sum) with M titratable sites whose forms give their
+ * atoms different charges (section "Hamiltonian Interpolation Formulation").
+ * Validates everything, chooses no parameters on its own, generates the
+ * translation and lattice tables in float64 on the host, and allocates all
+ * device buffers.  charges[N] are the environment charges; entries at site
+ * atoms are ignored.  sites may be NULL (plain FMM).  Errors: MAHI_EINVAL for
+ * NULL pointers, non-finite values or a bad site table (atom index out of
+ * range, atoms shared by two sites); MAHI_ERANGE for sizes outside the limits
+ * of mahi_opts and mahi_sites; MAHI_EDEVICE without a gfx950 device;
+ * MAHI_ENOMEM when an allocation fails.  *out is NULL on error.            */
 mahi_status mahi_create(mahi_ctx **out, const mahi_box *box, int64_t n_atoms, const double *charges,
                         const mahi_sites *sites, const mahi_opts *opts);
 
-/* Set the per-form weights lambda-tilde[sum forms] (site-major, then form).
- * Values are used as given (no renormalisation; the formulation stays exact
- * off the simplex).  Non-finite values give MAHI_EINVAL.  Runs the charge
- * scaling on the device.                                                    */
+/* Set the per-form weights lambda-tilde[sum forms] (site-major, then form;
+ * eq lambda_tilde, whose sum over the forms of a site is 1 by eq constraint).
+ * Values are used as given (no renormalisation; the general formulation, eq
+ * iter_ham_lambda, stays exact off the simplex).  Non-finite values give
+ * MAHI_EINVAL and leave the context unchanged.  Runs the charge scaling
+ * qt = sum_r lt_r q^(s,r) at the site atoms on the device and waits for it.  */
 mahi_status mahi_set_lambda(mahi_ctx *ctx, const double *lambda_tilde);
 
 /* One evaluation: octree build, P2M, M2M, periodic lattice, M2L, L2L, L2P and
@@ -135,8 +144,13 @@ mahi_status mahi_set_lambda(mahi_ctx *ctx, const double *lambda_tilde);
  * then the per-site correction (paper, section "Multipole-Accelerated
  * Hamiltonian Interpolation": eqs correction_scheme to C_B and the execution
  * order of section "Execution of MAHI").
+ * With forces = NULL only the potential is formed (the near field and the
+ * local expansions without their gradients): the energy, dvdl, dedq and the
+ * charge-interpolation outputs need nothing else.
  * Without MAHI_DEVICE_IO the call copies host inputs and outputs and waits
- * for the GPU.                                                              */
+ * for the GPU.  Errors: MAHI_EINVAL (NULL args or xyz, unknown flags,
+ * non-finite host coordinates), MAHI_ESTATE before mahi_set_lambda (nothing is
+ * written), MAHI_EDEVICE for a HIP error.                                   */
 mahi_status mahi_eval(mahi_ctx *ctx, const mahi_eval_args *args);
 
 /* Replace the charges of every form of every site (same layout and checks as
@@ -224,6 +238,11 @@ void mahi_destroy(mahi_ctx *ctx);
 
 const char *mahi_strerror(mahi_status s);
 const char *mahi_last_error(const mahi_ctx *ctx);
+
+/* The hipStream_t the context's evaluations run on (mahi_opts.hip_stream, or
+ * the stream the context created when that was NULL), for callers that order
+ * their own work with MAHI_DEVICE_IO evaluations through events.            */
+mahi_status mahi_get_stream(const mahi_ctx *ctx, void **stream);
 
 /* Sizes a context was created with: n_atoms, n_sites, total forms, order,
  * depth, precision (NULL pointers are skipped).                              */

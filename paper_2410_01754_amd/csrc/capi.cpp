@@ -768,6 +768,12 @@ mahi_status mahi_dlambda(int n_lambda, const double *lambda, const double *dvdl,
 
 void mahi_destroy(mahi_ctx *ctx) { free_ctx(ctx); }
 
+mahi_status mahi_get_stream(const mahi_ctx *ctx, void **stream) {
+  if (!ctx || !stream) return MAHI_EINVAL;
+  *stream = static_cast<void *>(ctx->stream);
+  return MAHI_OK;
+}
+
 mahi_status mahi_info(const mahi_ctx *ctx, int64_t *n_atoms, int32_t *n_sites, int32_t *n_forms, int *order, int *depth,
                       int *precision) {
   if (!ctx) return MAHI_EINVAL;

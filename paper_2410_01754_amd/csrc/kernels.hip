@@ -314,10 +314,6 @@ __global__ void k_bin(const T *__restrict__ xyz, const T *__restrict__ qt, int64
   }
 }
 
-// Exclusive scan of leaf counts in one block of 1024 threads: rounds of 8192
-// counts are loaded coalesced into LDS, each thread scans 8 consecutive ones,
-// the block scans the thread sums (wave scans, then the 16 wave sums) and the
-// round's total carries into the next round.  start[nleaf] receives the total.
 // Exclusive prefix sum of the leaf counts in one block: thread t owns 32
 // consecutive leaves of a round of 32,768 (eight int4 loads and stores), the
 // block sums are scanned across waves.  The counts are cleared as they are
@@ -443,9 +439,16 @@ __global__ void __launch_bounds__(64) k_p2m(const Atom4<T> *__restrict__ sorted,
   const int leaf = blockIdx.x, lane = threadIdx.x;
   const int s0 = start[leaf], cnt = start[leaf + 1] - s0;
   constexpr int kMaxPer = ((kMaxOrder + 1) * (kMaxOrder + 1) + 63) / 64;
-  T acc[kMaxPer];
+  // float32: compensated sums (Knuth's two-sum, error terms in cmp).  A leaf's
+  // monopole is a sum of ~30 charges that take a few repeated values (water
+  // O and H), and plain float32 summation rounds those partial sums the same
+  // way in every leaf: the bias (~1e-7 e per leaf) adds up over the tree into
+  // the total charge seen by the far field and the lattice and shifts every
+  // potential by a constant.  Compensated sums round each coefficient once.
+  constexpr bool kComp = sizeof(T) == sizeof(float);
+  T acc[kMaxPer], cmp[kMaxPer];
 #pragma unroll
-  for (int i = 0; i < kMaxPer; ++i) acc[i] = T(0);
+  for (int i = 0; i < kMaxPer; ++i) acc[i] = cmp[i] = T(0);
   for (int c0 = 0; c0 < cnt; c0 += chunk) {
     const int nch = min(chunk, cnt - c0);
     if (lane < nch) {
@@ -461,15 +464,25 @@ __global__ void __launch_bounds__(64) k_p2m(const Atom4<T> *__restrict__ sorted,
 #pragma unroll
     for (int i = 0; i < kMaxPer; ++i) {
       const int k = lane + 64 * i;
-      if (k < K)
-        for (int r = 0; r < nch; ++r) acc[i] += rows[r * K + k];
+      if (k < K) {
+        for (int r = 0; r < nch; ++r) {
+          const T v = rows[r * K + k];
+          if constexpr (kComp) {
+            const T t = acc[i] + v, bp = t - acc[i];
+            cmp[i] += (acc[i] - (t - bp)) + (v - bp);
+            acc[i] = t;
+          } else {
+            acc[i] += v;
+          }
+        }
+      }
     }
     __syncthreads();
   }
 #pragma unroll
   for (int i = 0; i < kMaxPer; ++i) {
     const int k = lane + 64 * i;
-    if (k < K) Mleaf[(int64_t)leaf * KS + k] = acc[i];
+    if (k < K) Mleaf[(int64_t)leaf * KS + k] = acc[i] + cmp[i];
   }
   if (qds) {
     const Geom g = *gp;
@@ -936,7 +949,8 @@ __device__ __forceinline__ P2PPass p2p_pass_shape(int nt, int &M) {
   return {max(P, 1), 64 / max(P, 1)};
 }
 
-template <class T, int M, bool SELF>
+// FIELD = false: potential only (evaluations that return no forces).
+template <class T, int M, bool SELF, bool FIELD>
 __device__ __forceinline__ void p2p_pair(const Atom4<T> &o, const T (&px)[M], const T (&py)[M], const T (&pz)[M],
                                          T (&phi)[M], T (&ex)[M], T (&ey)[M], T (&ez)[M]) {
 #pragma unroll
@@ -947,16 +961,18 @@ __device__ __forceinline__ void p2p_pair(const Atom4<T> &o, const T (&px)[M], co
     if (SELF) ri = r2 > T(0) ? ri : T(0);
     const T qr = o.q * ri;
     phi[m] += qr;
-    const T f = qr * ri * ri;
-    ex[m] += f * rx;
-    ey[m] += f * ry;
-    ez[m] += f * rz;
+    if constexpr (FIELD) {
+      const T f = qr * ri * ri;
+      ex[m] += f * rx;
+      ey[m] += f * ry;
+      ez[m] += f * rz;
+    }
   }
 }
 
 // Sources s[g], s[g + G], ... of one neighbour leaf (cnt atoms), with the next
 // two loaded before the current two are used.
-template <class T, int M, bool SELF>
+template <class T, int M, bool SELF, bool FIELD>
 __device__ __forceinline__ void p2p_run(const Atom4<T> *__restrict__ s, int cnt, int g, int G, const T (&px)[M],
                                         const T (&py)[M], const T (&pz)[M], T (&phi)[M], T (&ex)[M], T (&ey)[M],
                                         T (&ez)[M]) {
@@ -966,12 +982,12 @@ __device__ __forceinline__ void p2p_run(const Atom4<T> *__restrict__ s, int cnt,
   Atom4<T> o0 = s[j], o1 = s[min(j + G, last)];
   for (; j + G < cnt; j += 2 * G) {
     const Atom4<T> n0 = s[min(j + 2 * G, last)], n1 = s[min(j + 3 * G, last)];
-    p2p_pair<T, M, SELF>(o0, px, py, pz, phi, ex, ey, ez);
-    p2p_pair<T, M, SELF>(o1, px, py, pz, phi, ex, ey, ez);
+    p2p_pair<T, M, SELF, FIELD>(o0, px, py, pz, phi, ex, ey, ez);
+    p2p_pair<T, M, SELF, FIELD>(o1, px, py, pz, phi, ex, ey, ez);
     o0 = n0;
     o1 = n1;
   }
-  if (j < cnt) p2p_pair<T, M, SELF>(o0, px, py, pz, phi, ex, ey, ez);
+  if (j < cnt) p2p_pair<T, M, SELF, FIELD>(o0, px, py, pz, phi, ex, ey, ez);
 }
 
 template <class T>
@@ -982,7 +998,7 @@ __device__ __forceinline__ T shfl_t(T v, int src) {
 // One pass: targets [tp, tp + nt) (nt <= 64) against the 27 neighbour leaves
 // (start and count per neighbour in nb_st / nb_ct).  Lane u < nt receives the
 // sums for target u (leaf units) in acc.
-template <class T, int M>
+template <class T, int M, bool FIELD>
 __device__ __forceinline__ void p2p_wave(const Atom4<T> *__restrict__ sorted, const int *nb_st, const int *nb_ct,
                                          int tp, int nt, int lane, P2PPass ps, T (&acc)[4]) {
   const int p = lane % ps.P, g = lane / ps.P;
@@ -1010,8 +1026,8 @@ __device__ __forceinline__ void p2p_wave(const Atom4<T> *__restrict__ sorted, co
         py[m] = qy[m] - sy;
         pz[m] = qz[m] - sz;
       }
-      if (r == 13) p2p_run<T, M, true>(sorted + nb_st[r], cnt, g, ps.G, px, py, pz, phi, ex, ey, ez);
-      else p2p_run<T, M, false>(sorted + nb_st[r], cnt, g, ps.G, px, py, pz, phi, ex, ey, ez);
+      if (r == 13) p2p_run<T, M, true, FIELD>(sorted + nb_st[r], cnt, g, ps.G, px, py, pz, phi, ex, ey, ez);
+      else p2p_run<T, M, false, FIELD>(sorted + nb_st[r], cnt, g, ps.G, px, py, pz, phi, ex, ey, ez);
     }
   }
   // lane u (target u = p' + m' P) gathers its sums from lanes g P + p' in group order
@@ -1022,9 +1038,11 @@ __device__ __forceinline__ void p2p_wave(const Atom4<T> *__restrict__ sorted, co
     for (int gg = 0; gg < ps.G; ++gg) {
       const int sl = gg * ps.P + pu;
       s0 += shfl_t(phi[m], sl);
-      s1 += shfl_t(ex[m], sl);
-      s2 += shfl_t(ey[m], sl);
-      s3 += shfl_t(ez[m], sl);
+      if constexpr (FIELD) {
+        s1 += shfl_t(ex[m], sl);
+        s2 += shfl_t(ey[m], sl);
+        s3 += shfl_t(ez[m], sl);
+      }
     }
     if (mu == m) {
       acc[0] += s0;
@@ -1035,7 +1053,7 @@ __device__ __forceinline__ void p2p_wave(const Atom4<T> *__restrict__ sorted, co
   }
 }
 
-template <class T, int PT>
+template <class T, int PT, bool FIELD>
 __global__ void __launch_bounds__(64) k_p2p_l2p(const Atom4<T> *__restrict__ sorted, const int *__restrict__ start,
                                                 const int *__restrict__ perm, const T *__restrict__ Lleaf,
                                                 const Geom *__restrict__ gp, P2PArgs a, T *__restrict__ phi_sorted,
@@ -1074,7 +1092,7 @@ __global__ void __launch_bounds__(64) k_p2p_l2p(const Atom4<T> *__restrict__ sor
   }
   for (int e = lane; e < a.K; e += 64) loc[e] = Lleaf[(int64_t)leaf * a.KS + e];
   __syncthreads();
-  if (a.dloc) {
+  if (FIELD && a.dloc) {
     // gradient coefficients Dx, Dy, Dz in the real packing of L (degrees < p)
     const int nd = a.p * a.p;
     for (int k = lane; k < nd; k += 64) {
@@ -1103,15 +1121,21 @@ __global__ void __launch_bounds__(64) k_p2p_l2p(const Atom4<T> *__restrict__ sor
     int M;
     const P2PPass ps = p2p_pass_shape(nt, M);
     T acc[4] = {T(0), T(0), T(0), T(0)};
-    if (M == 1) p2p_wave<T, 1>(sorted, nb_st, nb_ct, tp, nt, lane, ps, acc);
-    else if (M == 2) p2p_wave<T, 2>(sorted, nb_st, nb_ct, tp, nt, lane, ps, acc);
-    else p2p_wave<T, 3>(sorted, nb_st, nb_ct, tp, nt, lane, ps, acc);
+    if (M == 1) p2p_wave<T, 1, FIELD>(sorted, nb_st, nb_ct, tp, nt, lane, ps, acc);
+    else if (M == 2) p2p_wave<T, 2, FIELD>(sorted, nb_st, nb_ct, tp, nt, lane, ps, acc);
+    else p2p_wave<T, 3, FIELD>(sorted, nb_st, nb_ct, tp, nt, lane, ps, acc);
     if (lane < nt) {
       const int ti = tp + lane;
       const Atom4<T> me = sorted[ti];
       T pf = T(0), gx = T(0), gy = T(0), gz = T(0);
       const int p = PT > 0 ? PT : a.p;
-      if (a.dloc) {
+      if constexpr (!FIELD) {
+        visit_regular<PT>(p, me.x, me.y, me.z, [&](int nn, int m, T re, T im) {
+          const int i0 = ridx_d(nn, m, 0);
+          if (m) pf += T(2) * (loc[i0] * re + loc[i0 + 1] * im);
+          else pf += loc[i0] * re;
+        });
+      } else if (a.dloc) {
         visit_regular<PT>(p, me.x, me.y, me.z, [&](int nn, int m, T re, T im) {
           const int i0 = ridx_d(nn, m, 0);
           if (m) {
@@ -1159,7 +1183,7 @@ __global__ void __launch_bounds__(64) k_p2p_l2p(const Atom4<T> *__restrict__ sor
       const double q = (double)me.q;
       phi_sorted[ti] = (T)ph;
       const int64_t u = perm[ti];
-      if (F) {
+      if (FIELD && F) {
         F[3 * u + 0] = (T)(a.ke * q * E[0]);
         F[3 * u + 1] = (T)(a.ke * q * E[1]);
         F[3 * u + 2] = (T)(a.ke * q * E[2]);
@@ -1704,12 +1728,20 @@ void launch_p2p(const Atom4<T> *sorted, const int *start, const int *perm, const
   // gradient coefficients in LDS when L, Dx, Dy, Dz fit in 16 KB
   a.dloc = (size_t)4 * a.K * sizeof(T) <= 16384 ? 1 : 0;
   const size_t lds = (size_t)(a.dloc ? 4 : 1) * a.K * sizeof(T);
-  if (p == 8)
-    hipLaunchKernelGGL((k_p2p_l2p<T, 8>), dim3(p2p_blocks<T>(d)), dim3(64), lds, st, sorted, start, perm, Lleaf, g, a,
-                       phi_sorted, F, pot_user, epart);
+  // without forces only the potential is formed (near field and local expansion)
+  const dim3 grid(p2p_blocks<T>(d)), block(64);
+  if (p == 8 && F)
+    hipLaunchKernelGGL((k_p2p_l2p<T, 8, true>), grid, block, lds, st, sorted, start, perm, Lleaf, g, a, phi_sorted, F,
+                       pot_user, epart);
+  else if (p == 8)
+    hipLaunchKernelGGL((k_p2p_l2p<T, 8, false>), grid, block, lds, st, sorted, start, perm, Lleaf, g, a, phi_sorted, F,
+                       pot_user, epart);
+  else if (F)
+    hipLaunchKernelGGL((k_p2p_l2p<T, 0, true>), grid, block, lds, st, sorted, start, perm, Lleaf, g, a, phi_sorted, F,
+                       pot_user, epart);
   else
-    hipLaunchKernelGGL((k_p2p_l2p<T, 0>), dim3(p2p_blocks<T>(d)), dim3(64), lds, st, sorted, start, perm, Lleaf, g, a,
-                       phi_sorted, F, pot_user, epart);
+    hipLaunchKernelGGL((k_p2p_l2p<T, 0, false>), grid, block, lds, st, sorted, start, perm, Lleaf, g, a, phi_sorted, F,
+                       pot_user, epart);
 }
 
 template <class T>

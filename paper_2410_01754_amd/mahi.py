@@ -90,6 +90,8 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
                               ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int),
                               ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)]
     lib.mahi_info.restype = ctypes.c_int
+    lib.mahi_get_stream.argtypes = [vp, ctypes.POINTER(vp)]
+    lib.mahi_get_stream.restype = ctypes.c_int
     lib.mahi_host_selftest.argtypes = [ctypes.c_int, ctypes.POINTER(ctypes.c_double)]
     lib.mahi_host_selftest.restype = ctypes.c_int
     lib.mahi_device_selftest.argtypes = [ctypes.c_int, ctypes.POINTER(ctypes.c_double)]
@@ -321,6 +323,12 @@ class Mahi:
         out = np.zeros(count, dtype=dt)
         _check(self._lib.mahi_debug_copy(self._h, which, out.ctypes.data, count), self._h)
         return out
+
+    def stream_handle(self) -> int:
+        """The hipStream_t (as an int) that this evaluator's evaluations run on."""
+        v = ctypes.c_void_p()
+        _check(self._lib.mahi_get_stream(self._h, ctypes.byref(v)), self._h)
+        return int(v.value or 0)
 
     def info(self):
         n = ctypes.c_int64()

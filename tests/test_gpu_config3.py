@@ -1,0 +1,165 @@
+"""Differentiation on the 100,717-atom periodic system (64 sites of 2 and 3
+forms, 10 nm cube, depth 4) through the torch.autograd binding (run on an
+MI355X).
+
+* Gradients of the energy in positions, weights lambda-tilde and form charges
+  (paper, section "Calculation of Forces on lambda Particles"; the per-form
+  part of the mapping K in the appendix) against the oracle's analytic
+  derivatives of the general formulation (reference values at every site atom
+  and 4,000 sampled atoms), in both autograd modes (derivatives recomputed in
+  the backward pass, or kept from the forward pass).
+* Central differences of the float64 GPU energy at 200 seeded (atom, axis)
+  coordinates (h = 1e-4 nm), at every weight (h = 1e-4) and at 60 sampled form
+  charges (h = 1e-4 e), against the derivatives the same path returns.
+Relative RMS ||a - b|| / ||b|| as in the parity tests.
+"""
+import os
+
+import numpy as np
+import pytest
+
+from synth import make_config
+
+pytestmark = pytest.mark.gpu
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+def rel(a, b):
+    a, b = np.asarray(a, float), np.asarray(b, float)
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def golden():
+    path = os.path.join(HERE, "golden", "config1_oracle.npz")
+    if not os.path.exists(path):
+        pytest.skip(f"{path} not generated")
+    return np.load(path)
+
+
+def evaluator(s, precision, order, depth):
+    import torch
+    import paper_2410_01754_amd as pkg
+    print(f"[gpu] {s.name} N={s.n_atoms} p={order} d={depth} prec={precision}", flush=True)
+    return pkg.from_system(s, precision=precision, order=order, depth=depth,
+                           stream=torch.cuda.current_stream().cuda_stream)
+
+
+@pytest.mark.parametrize("prec,order,tol,store", [(64, 16, 1e-6, False), (64, 16, 1e-6, True),
+                                                  (32, 16, 1e-6, False), (32, 8, 2e-4, True)])
+def test_autograd_matches_oracle(prec, order, tol, store):
+    import torch
+    from paper_2410_01754_amd.autograd import MahiEnergy, flat_form_charges
+    gd = golden()
+    s = make_config(1)
+    m = evaluator(s, prec, order, 4)
+    dt = torch.float32 if prec == 32 else torch.float64
+    x = torch.tensor(s.x, dtype=dt, device="cuda", requires_grad=True)
+    lt = torch.tensor(s.lam_flat(), dtype=torch.float64, requires_grad=True)
+    fq = torch.tensor(flat_form_charges(s), dtype=torch.float64, requires_grad=True)
+    e = MahiEnergy.apply(x, lt, fq, m, store)
+    (3.0 * e).backward()
+    m.close()
+    idx = gd["idx"]
+    ee = abs(e.item() - gd["energy"][0]) / abs(gd["energy"][0])
+    ef = rel(x.grad.cpu().numpy()[idx], -3.0 * gd["forces"])
+    el = rel(lt.grad.numpy(), 3.0 * gd["dvdl"])
+    eq = rel(fq.grad.numpy(), 3.0 * gd["dedq"])
+    print(f"autograd prec={prec} p={order} store={store}: E {ee:.3e} dx {ef:.3e} dlt {el:.3e} dq {eq:.3e}")
+    assert ee <= tol and ef <= tol and el <= tol and eq <= tol
+
+
+def test_recompute_and_store_give_the_same_gradients():
+    """The backward pass of the recompute mode evaluates with the forward pass's
+    weights even when the evaluator was used with other weights in between."""
+    import torch
+    from paper_2410_01754_amd.autograd import MahiEnergy
+    s = make_config(1)
+    m = evaluator(s, 32, 8, 4)
+    lam = s.lam_flat()
+    grads = []
+    for store in (True, False):
+        x = torch.tensor(s.x, device="cuda", requires_grad=True)
+        lt = torch.tensor(lam, dtype=torch.float64, requires_grad=True)
+        e = MahiEnergy.apply(x, lt, None, m, store)
+        m.set_lambda(lam[::-1].copy())  # another state before the backward pass
+        m.eval(s.x)
+        e.backward()
+        grads.append((e.item(), x.grad.cpu().numpy(), lt.grad.numpy()))
+    m.close()
+    # the recompute mode's forward pass forms the potential alone (same sums, rounding may differ)
+    assert abs(grads[0][0] - grads[1][0]) <= 1e-12 * abs(grads[0][0])
+    assert np.array_equal(grads[0][1], grads[1][1]) and np.array_equal(grads[0][2], grads[1][2])
+
+
+def _coordinate_samples(s, depth, h, n, seed):
+    """n distinct (atom, axis) pairs whose +-h moves stay inside the atom's leaf
+    (the tree, and with it the truncated expansion, changes across a leaf face)."""
+    rng = np.random.default_rng(seed)
+    leaf = s.box / 2 ** depth
+    out, seen = [], set()
+    while len(out) < n:
+        i, d = int(rng.integers(s.n_atoms)), int(rng.integers(3))
+        if (i, d) in seen:
+            continue
+        f = (float(s.x[i, d]) % s.box) / leaf
+        if min(f - np.floor(f), np.ceil(f) - f) * leaf <= 4 * h:
+            continue
+        seen.add((i, d))
+        out.append((i, d))
+    return out
+
+
+def test_central_differences_float64():
+    s = make_config(1)
+    m = evaluator(s, 64, 16, 4)
+    x = s.x.astype(np.float64)
+    base = m.eval(x, dedq=True)
+    energy = lambda xx: m.eval(xx, forces=False, dvdl=False)["energy"]  # noqa: E731
+    # positions: F = -dE/dx
+    h = 1e-4
+    fd, an = [], []
+    for i, d in _coordinate_samples(s, 4, h, 200, 1754):
+        xp, xm = x.copy(), x.copy()
+        xp[i, d] += h
+        xm[i, d] -= h
+        fd.append(-(energy(xp) - energy(xm)) / (2 * h))
+        an.append(base["forces"][i, d])
+    fd, an = np.array(fd), np.array(an)
+    fmax = np.abs(base["forces"]).max()
+    print(f"x: rel RMS {rel(fd, an):.3e}, max |diff| / max |F| {np.abs(fd - an).max() / fmax:.3e}")
+    assert rel(fd, an) <= 1e-6 and np.abs(fd - an).max() <= 1e-5 * fmax
+    # weights: every lambda-tilde (the energy is quadratic in them, so the
+    # central difference is exact up to rounding)
+    lam = s.lam_flat()
+    fd = []
+    for k in range(lam.shape[0]):
+        lp, lm = lam.copy(), lam.copy()
+        lp[k] += h
+        lm[k] -= h
+        m.set_lambda(lp)
+        ep = energy(x)
+        m.set_lambda(lm)
+        fd.append((ep - energy(x)) / (2 * h))
+    m.set_lambda(lam)
+    fd = np.array(fd)
+    print(f"lambda: rel RMS {rel(fd, base['dvdl']):.3e}")
+    assert rel(fd, base["dvdl"]) <= 1e-6
+    assert np.abs(fd - base["dvdl"]).max() <= 1e-6 * np.abs(base["dvdl"]).max()
+    # form charges (quadratic as well)
+    fq = np.concatenate([st.charges.reshape(-1) for st in s.sites])
+    ks = np.random.default_rng(1755).choice(fq.shape[0], 60, replace=False)
+    fd = []
+    for k in ks:
+        qp, qm = fq.copy(), fq.copy()
+        qp[k] += h
+        qm[k] -= h
+        m.set_form_charges(qp)
+        ep = energy(x)
+        m.set_form_charges(qm)
+        fd.append((ep - energy(x)) / (2 * h))
+    m.set_form_charges(fq)
+    m.close()
+    fd = np.array(fd)
+    print(f"form charges: rel RMS {rel(fd, base['dedq'][ks]):.3e}")
+    assert rel(fd, base["dedq"][ks]) <= 1e-6
+    assert np.abs(fd - base["dedq"][ks]).max() <= 1e-6 * np.abs(base["dedq"]).max()

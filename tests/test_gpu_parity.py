@@ -24,6 +24,47 @@ def rel(a, b):
     return float(np.linalg.norm(a - b) / np.linalg.norm(b))
 
 
+def tangent(dvdl, system):
+    """Per-site differences dV/dlambda-tilde_rho - dV/dlambda-tilde_0 (rho >= 1): the
+    combinations that enter the lambda forces (the paper's accuracy figures are
+    lambda-force deviations)."""
+    out, o = [], 0
+    for st in system.sites:
+        nf = st.charges.shape[0]
+        out.extend(dvdl[o + r] - dvdl[o] for r in range(1, nf))
+        o += nf
+    return np.array(out)
+
+
+def metrics(g, E, F, dv, system, idx=None):
+    """Relative RMS of F, dV/dlambda-tilde and its tangent; |dE|/|E|; and for each of
+    F, dV/dlambda-tilde and the tangent the largest absolute error in units of
+    the RMS of the reference values."""
+    f = g["forces"] if idx is None else g["forces"][idx]
+    F, dv = np.asarray(F, float), np.asarray(dv, float)
+    tg, tr = tangent(g["dvdl"], system), tangent(dv, system)
+    rms = lambda v: float(np.sqrt(np.mean(np.square(v))))  # noqa: E731
+    m = {"E": abs(g["energy"] - E) / abs(E), "F": rel(f, F), "dvdl": rel(g["dvdl"], dv), "tangent": rel(tg, tr),
+         "F_max": float(np.abs(f - F).max()) / rms(F), "dvdl_max": float(np.abs(g["dvdl"] - dv).max()) / rms(dv),
+         "tangent_max": float(np.abs(tg - tr).max()) / rms(tr)}
+    print("  ".join(f"{k} {v:.3e}" for k, v in m.items()), flush=True)
+    return m
+
+
+# The largest single error of a compared quantity may exceed the RMS bound by
+# the tail of the error distribution (atoms near leaf corners, sites across
+# leaf faces), not by orders of magnitude: one grossly wrong atom or form
+# fails this even when the RMS over thousands of values passes.
+MAX_OVER_RMS = 25.0
+
+
+def check(m, tol):
+    for k in ("E", "F", "dvdl", "tangent"):
+        assert m[k] <= tol, (k, m[k], tol)
+    for k in ("F_max", "dvdl_max", "tangent_max"):
+        assert m[k] <= MAX_OVER_RMS * tol, (k, m[k], MAX_OVER_RMS * tol)
+
+
 def gpu_eval(system, precision, order, depth, potential=False):
     import paper_2410_01754_amd as pkg
     print(f"[gpu] {system.name} N={system.n_atoms} p={order} d={depth} prec={precision}", flush=True)
@@ -178,21 +219,16 @@ def _golden(k):
     return np.load(path)
 
 
-@pytest.mark.parametrize("prec,order,tol", [
-    (32, 8, 2e-4), (64, 8, 2e-4), (64, 16, 1e-6),
-    pytest.param(32, 16, 1e-6, marks=pytest.mark.xfail(
-        reason="float32 rounding floor of the far field (~1.2e-6 in F, ~8.5e-6 in dV/dlambda-tilde) lies above "
-               "1e-6", strict=False)),
-])
+@pytest.mark.parametrize("prec,order,tol", [(32, 8, 2e-4), (64, 8, 2e-4), (64, 16, 1e-6), (32, 16, 1e-6)])
 def test_config1(prec, order, tol):
+    """Config 1 (100,717 atoms, 64 sites of 2 and 3 forms), depth 4: the float32
+    and float64 paths at the production order 8 (2e-4) and at order 16 (1e-6),
+    against oracle values at every site atom and 4,000 sampled atoms."""
     gd = _golden(1)
     s = make_config(1)
     g = gpu_eval(s, prec, order, 4)
-    idx = gd["idx"]
-    ef, ed = rel(g["forces"][idx], gd["forces"]), rel(g["dvdl"], gd["dvdl"])
-    ee = abs(g["energy"] - gd["energy"][0]) / abs(gd["energy"][0])
-    print(f"config1 prec={prec} p={order}: E {ee:.3e} F {ef:.3e} dVdl {ed:.3e}")
-    assert ef <= tol and ed <= tol and ee <= tol
+    print(f"config1 prec={prec} p={order}:")
+    check(metrics(g, gd["energy"][0], gd["forces"], gd["dvdl"], s, gd["idx"]), tol)
 
 
 def test_config2_full_size_sampled():
@@ -201,11 +237,8 @@ def test_config2_full_size_sampled():
     gd = _golden(2)
     s = make_config(2)
     g = gpu_eval(s, 32, 8, 5)
-    idx = gd["idx"]
-    ef, ed = rel(g["forces"][idx], gd["forces"]), rel(g["dvdl"], gd["dvdl"])
-    ee = abs(g["energy"] - gd["energy"][0]) / abs(gd["energy"][0])
-    print(f"config2 fp32 p=8: E {ee:.3e} F {ef:.3e} dVdl {ed:.3e}")
-    assert ef <= 2e-4 and ed <= 2e-4 and ee <= 2e-4
+    print("config2 fp32 p=8:")
+    check(metrics(g, gd["energy"][0], gd["forces"], gd["dvdl"], s, gd["idx"]), 2e-4)
 
 
 def test_config2_full_size_float64():
@@ -214,8 +247,5 @@ def test_config2_full_size_float64():
     gd = _golden(2)
     s = make_config(2)
     g = gpu_eval(s, 64, 8, 5)
-    idx = gd["idx"]
-    ef, ed = rel(g["forces"][idx], gd["forces"]), rel(g["dvdl"], gd["dvdl"])
-    ee = abs(g["energy"] - gd["energy"][0]) / abs(gd["energy"][0])
-    print(f"config2 fp64 p=8: E {ee:.3e} F {ef:.3e} dVdl {ed:.3e}")
-    assert ef <= 2e-4 and ed <= 2e-4 and ee <= 2e-4
+    print("config2 fp64 p=8:")
+    check(metrics(g, gd["energy"][0], gd["forces"], gd["dvdl"], s, gd["idx"]), 2e-4)
