@@ -185,6 +185,23 @@ typedef struct {
 } mahi_correct_args;
 mahi_status mahi_correct(mahi_ctx *ctx, const mahi_correct_args *args);
 
+/* mahi_correct without any allocation and without the context's scratch, for
+ * callers that cannot allocate device memory at the call (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc).
+ * Same operation, kernels and results as mahi_correct; args->flags must be
+ * MAHI_DEVICE_IO (device pointers only; the call never waits for the GPU).
+ * Its scratch (per-site energies, plus the site pass's work arrays when a
+ * site exceeds local memory: 8 doubles per site rounded up to 256 bytes, plus
+ * 8 * (4 maxa^2 + maxa K + 5 maxf K) bytes per site in that case, K =
+ * (order+1)^2) lives in a static device array of 8 MiB that every device
+ * holds for the life of the process; calls needing more return MAHI_ERANGE
+ * and do nothing.  All calls on one device share that array, so calls that
+ * overlap on one device (other threads, other streams) race; calls ordered on
+ * one stream do not.  Nothing in it needs to start at zero: every call writes
+ * what it reads.  MAHI_EINVAL for NULL args, xyz or potential and for flags
+ * other than MAHI_DEVICE_IO; MAHI_ESTATE before mahi_set_lambda.            */
+mahi_status mahi_correct_noalloc(mahi_ctx *ctx, const mahi_correct_args *args);
+
 /* Binary multi-form sites (paper, appendix: eqs lambda_list and
  * one_site_lambda and the mapping of derivatives that follows them; section
  * "Calculation of Forces on lambda Particles").  A site with 2^L forms is

@@ -425,8 +425,10 @@ mahi_status eval_impl(mahi_ctx *ctx, const mahi_eval_args *a) {
 // Site correction on a potential from another solver: k_site reads ke * V from
 // `potential` (user order) instead of the tree's potential; the energy is the
 // sum of the per-site corrections.
+// dE_site [M] and ws (M * site_ws_stride doubles, or null when the site pass
+// keeps its work arrays in local memory) are the call's scratch.
 template <class T>
-mahi_status correct_impl(mahi_ctx *ctx, const mahi_correct_args *a) {
+mahi_status correct_impl(mahi_ctx *ctx, const mahi_correct_args *a, double *dE_site, double *ws) {
   const bool dev = (a->flags & MAHI_DEVICE_IO) != 0;
   const int64_t N = ctx->N;
   hipStream_t st = ctx->stream;
@@ -448,10 +450,10 @@ mahi_status correct_impl(mahi_ctx *ctx, const mahi_correct_args *a) {
   double *dedq = a->dedq ? (dev ? a->dedq : ctx->dedq) : nullptr;
   if (ctx->M > 0) {
     SiteArgs s = site_args<T>(ctx);
-    const SiteIO<T> io{nullptr, pot, F, dvdl, ctx->dE_site, dedq, nullptr, ctx->site_ws, ctx->site_ws_stride};
+    const SiteIO<T> io{nullptr, pot, F, dvdl, dE_site, dedq, nullptr, ws, ctx->site_ws_stride};
     launch_site<T>(s, xyz, ctx->slot_of, ctx->geom, ctx->LamT, io, st);
   }
-  launch_finalize(nullptr, 0, ctx->dE_site, ctx->M, ctx->ke, E, nullptr, st);
+  launch_finalize(nullptr, 0, dE_site, ctx->M, ctx->ke, E, nullptr, st);
   HIP_TRY(hipGetLastError(), "kernel launch");
   if (!dev) {
     if (a->energy) HIP_TRY(hipMemcpyAsync(a->energy, ctx->E, sizeof(double), hipMemcpyDeviceToHost, st), "copy energy");
@@ -605,6 +607,13 @@ mahi_status mahi_create(mahi_ctx **out, const mahi_box *box, int64_t n_atoms, co
   if (hipGetDeviceProperties(&prop, dev) != hipSuccess) return bad(MAHI_EDEVICE, "hipGetDeviceProperties failed");
   if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
     return bad(MAHI_EDEVICE, std::string("built for gfx950, found ") + prop.gcnArchName);
+  {
+    // the allocation-free correction's static scratch: its address on this
+    // device, looked up once with the device current
+    void *sp = nullptr;
+    const hipError_t e = static_scratch(dev, &sp);
+    if (e != hipSuccess) return bad(MAHI_EDEVICE, std::string("static scratch: ") + hip_msg(e));
+  }
   mahi_ctx *ctx = new (std::nothrow) mahi_ctx;
   if (!ctx) return bad(MAHI_ENOMEM, "host allocation failed");
   ctx->N = n_atoms;
@@ -691,7 +700,30 @@ mahi_status mahi_correct(mahi_ctx *ctx, const mahi_correct_args *a) {
     if (!(f32 ? all_finite<float>(a->potential, ctx->N) : all_finite<double>(a->potential, ctx->N)))
       return ctx->fail(MAHI_EINVAL, "non-finite potential");
   }
-  return ctx->prec == 32 ? correct_impl<float>(ctx, a) : correct_impl<double>(ctx, a);
+  return ctx->prec == 32 ? correct_impl<float>(ctx, a, ctx->dE_site, ctx->site_ws)
+                         : correct_impl<double>(ctx, a, ctx->dE_site, ctx->site_ws);
+}
+
+mahi_status mahi_correct_noalloc(mahi_ctx *ctx, const mahi_correct_args *a) {
+  if (!ctx) return MAHI_EINVAL;
+  if (!a || !a->xyz || !a->potential) return ctx->fail(MAHI_EINVAL, "args, args->xyz and args->potential must not be NULL");
+  if (a->flags != MAHI_DEVICE_IO)
+    return ctx->fail(MAHI_EINVAL, "mahi_correct_noalloc takes device pointers only (flags = MAHI_DEVICE_IO)");
+  if (!ctx->lambda_set) return ctx->fail(MAHI_ESTATE, "mahi_set_lambda must be called before mahi_correct_noalloc");
+  // scratch: per-site energies (rounded up to 256 bytes), then the site pass's
+  // work arrays when they exceed local memory
+  const size_t de_bytes = (sizeof(double) * (size_t)ctx->M + 255) / 256 * 256;
+  const size_t ws_bytes = ctx->site_ws ? sizeof(double) * (size_t)ctx->site_ws_stride * ctx->M : 0;
+  if (de_bytes + ws_bytes > kStaticScratchBytes)
+    return ctx->fail(MAHI_ERANGE, "the correction needs " + std::to_string(de_bytes + ws_bytes) +
+                                      " bytes of scratch; the static scratch holds " +
+                                      std::to_string(kStaticScratchBytes));
+  HIP_TRY(hipSetDevice(ctx->device), "set device");
+  void *sp = nullptr;
+  HIP_TRY(static_scratch(ctx->device, &sp), "static scratch");
+  double *dE_site = static_cast<double *>(sp);
+  double *ws = ws_bytes ? reinterpret_cast<double *>(static_cast<unsigned char *>(sp) + de_bytes) : nullptr;
+  return ctx->prec == 32 ? correct_impl<float>(ctx, a, dE_site, ws) : correct_impl<double>(ctx, a, dE_site, ws);
 }
 
 mahi_status mahi_set_form_charges(mahi_ctx *ctx, const double *form_charges) {

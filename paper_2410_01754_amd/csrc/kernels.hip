@@ -13,6 +13,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <mutex>
 
 #include "device_common.hpp"
 #include "kernels.hpp"
@@ -1500,6 +1501,34 @@ __global__ void __launch_bounds__(1024) k_finalize(const double *__restrict__ ep
     *E = ke * s[0];
     if (E_qi) *E_qi = ke * sq[0];
   }
+}
+
+// ---------------------------------------------------------------------------
+// Static scratch of the allocation-free correction: per-site energies and the
+// site pass's work arrays of one call.  Every device the library runs on holds
+// its own copy for the life of the process.  In host code `scratch` is only a
+// stand-in for the symbol: its device address comes from hipGetSymbolAddress
+// and is kept per device.
+// ---------------------------------------------------------------------------
+static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices] = {};
+}  // namespace
+
+hipError_t static_scratch(int device, void **ptr) {
+  if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[device]) {
+    void *p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    g_scratch_ptr[device] = p;
+  }
+  *ptr = g_scratch_ptr[device];
+  return hipSuccess;
 }
 
 // ---------------------------------------------------------------------------

@@ -113,6 +113,11 @@ void launch_site(const SiteArgs &s, const T *xyz, const int *slot_of, const Geom
 void launch_finalize(const double *epart, int nb, const double *dE_site, int ns, double ke, double *E, double *E_qi,
                      hipStream_t st);
 size_t site_lds_bytes(int p, int maxa, int maxf, bool with_d);
+// Static device scratch of the allocation-free correction (mahi_correct_noalloc):
+// its size, and its device address on `device` (looked up once per device with
+// that device current; later calls return the kept address).
+constexpr size_t kStaticScratchBytes = size_t(8) << 20;
+hipError_t static_scratch(int device, void **ptr);
 // whether the site pass keeps its work arrays in local memory (else a global workspace
 // of site_lds_bytes(p, maxa, maxf, true) per site)
 bool site_in_lds(int p, int maxa, int maxf);

@@ -111,6 +111,8 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.mahi_set_form_charges.restype = ctypes.c_int
     lib.mahi_correct.argtypes = [vp, ctypes.POINTER(_CorrectArgs)]
     lib.mahi_correct.restype = ctypes.c_int
+    lib.mahi_correct_noalloc.argtypes = [vp, ctypes.POINTER(_CorrectArgs)]
+    lib.mahi_correct_noalloc.restype = ctypes.c_int
     dp = ctypes.POINTER(ctypes.c_double)
     lib.mahi_lambda_tilde.argtypes = [ctypes.c_int, dp, dp]
     lib.mahi_lambda_tilde.restype = ctypes.c_int
@@ -298,6 +300,14 @@ class Mahi:
         args = _CorrectArgs(xyz_ptr, potential_ptr, energy_ptr or None, forces_ptr or None, dvdl_ptr or None,
                             dedq_ptr or None, MAHI_DEVICE_IO)
         _check(self._lib.mahi_correct(self._h, ctypes.byref(args)), self._h)
+
+    def correct_device_noalloc(self, xyz_ptr: int, potential_ptr: int, energy_ptr: int, forces_ptr: int = 0,
+                               dvdl_ptr: int = 0, dedq_ptr: int = 0):
+        """correct_device without any allocation (mahi_correct_noalloc: its scratch is
+        a static device array shared by every call on the device)."""
+        args = _CorrectArgs(xyz_ptr, potential_ptr, energy_ptr or None, forces_ptr or None, dvdl_ptr or None,
+                            dedq_ptr or None, MAHI_DEVICE_IO)
+        _check(self._lib.mahi_correct_noalloc(self._h, ctypes.byref(args)), self._h)
 
     def profile_begin(self, max_evals: int):
         _check(self._lib.mahi_profile_begin(self._h, int(max_evals)), self._h)
