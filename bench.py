@@ -109,8 +109,10 @@ def time_evals(m, x_dev, out, steps, warmup, profile=False):
 
 def batch_leg(steps: int):
     """96 periodic systems of 3k..60k atoms (log-uniform), each with the autotuned
-    order and depth for a 2e-4 target in float32: per-system latency alone and
-    the throughput of one eager batch (mahi_batch_eval) over all of them."""
+    order and depth for a 2e-4 target in float32: per-system latency alone, and
+    the batch over all of them as a fork/join of the systems' own evaluations,
+    as packed launches (one launch per stage over every system) and as those
+    launches replayed from a HIP graph (the headline of the leg)."""
     import torch
     import paper_2410_01754_amd as pkg
     from synth import make_batch
@@ -134,25 +136,41 @@ def batch_leg(steps: int):
         torch.cuda.synchronize()
         lat.append((time.perf_counter() - t0) / 3)
     lat = np.array(lat)
-    b = pkg.Batch(mods, use_graph=False)
     args = [{"xyz": a, "energy": e, "forces": f, "dvdl": v} for a, e, f, v in ptr]
-    b.eval_device(args)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(steps):
-        b.eval_device(args)
-    torch.cuda.synchronize()
-    tb = (time.perf_counter() - t0) / steps
-    b.close()
+
+    def timed(batch):
+        batch.eval_device(args)
+        torch.cuda.synchronize()
+        per = []
+        for _ in range(steps):
+            t0 = time.perf_counter()
+            batch.eval_device(args)
+            torch.cuda.synchronize()
+            per.append(time.perf_counter() - t0)
+        batch.close()
+        per = np.array(per)
+        return float(per.mean()), per
+
+    t_fj, _ = timed(pkg.Batch(mods))
+    t_pk, _ = timed(pkg.Batch(mods, packed=True))
+    t_gr, per_gr = timed(pkg.Batch(mods, packed=True, use_graph=True))
     depths = [m.info()["depth"] for m in mods]
+    orders = [m.info()["order"] for m in mods]
     for m in mods:
         m.close()
-    return {"systems": len(systems), "atoms": int(n.sum()), "mode": "eager (one fork/join, per-system streams)",
-            "batch_ms": tb * 1e3, "atom_evals_per_s": float(n.sum() / tb),
+    return {"systems": len(systems), "atoms": int(n.sum()),
+            "mode": "packed launches captured in one HIP graph (every stage one launch over all systems)",
+            "batch_ms": t_gr * 1e3, "atom_evals_per_s": float(n.sum() / t_gr),
+            # every system of a packed batch completes with the batch
+            "batch_latency_us_p50": float(np.percentile(per_gr, 50) * 1e6),
+            "batch_latency_us_p99": float(np.percentile(per_gr, 99) * 1e6),
+            "packed_eager_ms": t_pk * 1e3, "fork_join_ms": t_fj * 1e3,
+            "fork_join_atom_evals_per_s": float(n.sum() / t_fj),
             "single_latency_us_p50": float(np.percentile(lat, 50) * 1e6),
             "single_latency_us_p99": float(np.percentile(lat, 99) * 1e6),
             "sequential_atom_evals_per_s": float(n.sum() / lat.sum()),
-            "depth_histogram": {str(d): depths.count(d) for d in sorted(set(depths))}}
+            "depth_histogram": {str(d): depths.count(d) for d in sorted(set(depths))},
+            "order_histogram": {str(o): orders.count(o) for o in sorted(set(orders))}}
 
 
 def oracle_kspace_work(n: int, edge: float) -> float:

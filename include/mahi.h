@@ -219,18 +219,30 @@ mahi_status mahi_dlambda(int n_lambda, const double *lambda, const double *dvdl 
 /* Batched evaluation of many systems (small systems leave most of the GPU
  * idle in a single evaluation; the paper's small-system regime, sections
  * "Scaling with Number of Particles" and "Performance").  A batch holds n
- * distinct contexts of one device and evaluates them together: every call
- * forks from `hip_stream` (the batch's origin stream, NULL = a stream the
- * batch creates), runs each context's evaluation on that context's own
- * streams, and joins back, so later work on the origin stream sees every
- * output.  use_graph = 1 (capture the whole fork/join once into a HIP graph
- * and replay it, capturing again when a pointer in args changes) is disabled
- * in this build and returns MAHI_EUNSUPPORTED; use_graph = 0 issues every
- * kernel eagerly.
+ * distinct contexts of one device and evaluates them together; later work on
+ * `hip_stream` (the batch's origin stream, NULL = a stream the batch creates)
+ * sees every output.  flags:
+ *   0: every call forks from the origin stream, runs each context's own
+ *      evaluation on that context's streams and joins back (outputs identical
+ *      to evaluating each context alone);
+ *   MAHI_BATCH_PACKED: every stage of the evaluation is one launch over all
+ *      systems (octree build over the concatenated atoms, M2L of every level
+ *      of every system together, ...), on the origin stream only; the batch
+ *      owns the evaluation buffers (the contexts give their tables, charges,
+ *      sites and geometry).  Needs float32 periodic contexts of one order of
+ *      at most 8 whose sites fit in local memory (else MAHI_EUNSUPPORTED).
+ *      Results agree with single evaluations up to the summation order of
+ *      the M2L operator ranges;
+ *   MAHI_BATCH_PACKED | MAHI_BATCH_GRAPH: the packed launches are captured once
+ *      into a HIP graph and replayed (captured again when a pointer in args
+ *      changes; new weights or form charges need no new capture).
+ *   MAHI_BATCH_GRAPH alone returns MAHI_EUNSUPPORTED.
  * The contexts stay owned by the caller and must outlive the batch; while in
  * a batch they may still be used alone, but not concurrently with it.      */
+#define MAHI_BATCH_GRAPH 1u
+#define MAHI_BATCH_PACKED 2u
 typedef struct mahi_batch mahi_batch;
-mahi_status mahi_batch_create(mahi_batch **out, mahi_ctx *const *ctxs, int n_ctx, int use_graph, void *hip_stream);
+mahi_status mahi_batch_create(mahi_batch **out, mahi_ctx *const *ctxs, int n_ctx, int flags, void *hip_stream);
 /* args[n_ctx], each with MAHI_DEVICE_IO (device pointers; the call returns
  * without waiting).  Every context must have its lambda-tilde set and no stage
  * profiling open.  MAHI_EINVAL for host-memory arguments.                   */

@@ -52,6 +52,7 @@ struct mahi_ctx {
   void *xyz = nullptr, *qt = nullptr, *F = nullptr, *pot = nullptr, *phi_sorted = nullptr;
   void *part = nullptr;  // float32 M2L partial locals, one array per operator range
   void *packed = nullptr;  // leaf-local atoms in input order (octree build)
+  void *packed_lo = nullptr, *sorted_lo = nullptr;  // float32 above order 8: coordinate residuals
   void *Mc = nullptr, *Lc = nullptr, *m2l = nullptr, *m2m = nullptr, *l2l = nullptr, *sorted = nullptr;
   double *LamT = nullptr, *qds = nullptr, *epart = nullptr, *dE_site = nullptr, *dvdl = nullptr, *E = nullptr;
   double *bbox = nullptr, *lam = nullptr, *fq = nullptr;
@@ -109,10 +110,26 @@ struct mahi_batch {
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
   std::vector<mahi_eval_args> captured;  // the arguments baked into the graph
+  // packed mode: every stage one launch over all systems, on `root` only
+  bool packed = false;
+  PackedPlan pp{};
+  std::vector<DevBuf> bufs;           // the batch's own device memory
+  std::vector<PackedSys> sys_host;    // per-system descriptors (argument pointers filled per call)
+  PackedSys *sys_dev = nullptr;
+  std::vector<mahi_eval_args> table;  // the arguments the device descriptors hold
   std::string err;
   mahi_status fail(mahi_status s, const std::string &m) {
     err = m;
     return s;
+  }
+  template <class P>
+  hipError_t alloc(P *&ptr, size_t bytes) {
+    void *q = nullptr;
+    hipError_t e = hipMalloc(&q, bytes < 16 ? 16 : bytes);
+    if (e != hipSuccess) return e;
+    bufs.push_back({q, bytes});
+    ptr = static_cast<P *>(q);
+    return hipSuccess;
   }
 };
 
@@ -188,6 +205,10 @@ mahi_status setup_device(mahi_ctx *ctx, const std::vector<double> &q_env, const 
   HIP_TRY(ctx->alloc(ctx->phi_sorted, sizeof(T) * N), "alloc potential (sorted)");
   HIP_TRY(ctx->alloc(ctx->sorted, sizeof(Atom4<T>) * N), "alloc sorted atoms");
   HIP_TRY(ctx->alloc(ctx->packed, sizeof(Atom4<T>) * N), "alloc packed atoms");
+  if (f32 && p > 8) {
+    HIP_TRY(ctx->alloc(ctx->packed_lo, sizeof(Atom4<T>) * N), "alloc coordinate residuals");
+    HIP_TRY(ctx->alloc(ctx->sorted_lo, sizeof(Atom4<T>) * N), "alloc coordinate residuals");
+  }
   // one extra all-zero box row (the source of empty M2L slots); pads stay zero
   HIP_TRY(ctx->alloc(ctx->Mc, sizeof(T) * (nbox + 1) * KS), "alloc multipoles");
   HIP_TRY(ctx->alloc(ctx->Lc, sizeof(T) * (nbox + 1) * KS), "alloc locals");
@@ -343,7 +364,8 @@ mahi_status eval_impl(mahi_ctx *ctx, const mahi_eval_args *a) {
   ctx->mark(0);
   if (!ctx->periodic) launch_bbox<T>(xyz, N, ctx->bbox, ctx->nbbox, ctx->geom, st);
   TreeBufs<T> tb{ctx->key,     ctx->count,   ctx->start, ctx->tmp, ctx->perm, ctx->slot_of,
-                 static_cast<Atom4<T> *>(ctx->packed), static_cast<Atom4<T> *>(ctx->sorted)};
+                 static_cast<Atom4<T> *>(ctx->packed), static_cast<Atom4<T> *>(ctx->sorted),
+                 static_cast<Atom4<T> *>(ctx->packed_lo), static_cast<Atom4<T> *>(ctx->sorted_lo)};
   launch_tree<T>(xyz, static_cast<const T *>(ctx->qt), N, ctx->geom, d, ctx->periodic, tb, st);
   ctx->mark(1);
   launch_p2m<T>(tb.sorted, ctx->start, nleaf, p, KS, Mc + level_offset(d) * KS, ctx->periodic ? ctx->qds : nullptr,
@@ -390,7 +412,7 @@ mahi_status eval_impl(mahi_ctx *ctx, const mahi_eval_args *a) {
   HIP_TRY(hipStreamWaitEvent(st, ctx->ev_join, 0), "join");
   for (int l = std::max(hl, l2l_first); l <= d; ++l) launch_updown<T>(Lc, Tl2l, p, KS, l - 1, false, st);
   ctx->mark(6);
-  launch_p2p<T>(tb.sorted, ctx->start, ctx->perm, Lc + level_offset(d) * KS, KS, ctx->geom, d, ctx->periodic, p, ctx->ke,
+  launch_p2p<T>(tb.sorted, tb.sorted_lo, ctx->start, ctx->perm, Lc + level_offset(d) * KS, KS, ctx->geom, d, ctx->periodic, p, ctx->ke,
                 static_cast<T *>(ctx->phi_sorted), F, pot, ctx->epart, st);
   ctx->mark(7);
   if (ctx->M > 0) {
@@ -480,20 +502,6 @@ bool all_finite(const void *p, int64_t n) {
     if (_e != hipSuccess) return b->fail(MAHI_EDEVICE, std::string(what) + ": " + hip_msg(_e)); \
   } while (0)
 
-// Fork from the origin stream into every context's stream, evaluate, join back.
-mahi_status batch_issue(mahi_batch *b, const mahi_eval_args *args) {
-  BATCH_TRY(hipEventRecord(b->fork, b->root), "batch fork");
-  for (size_t i = 0; i < b->ctxs.size(); ++i) {
-    mahi_ctx *ctx = b->ctxs[i];
-    BATCH_TRY(hipStreamWaitEvent(ctx->stream, b->fork, 0), "batch fork");
-    const mahi_status st = ctx->prec == 32 ? eval_impl<float>(ctx, &args[i]) : eval_impl<double>(ctx, &args[i]);
-    if (st != MAHI_OK) return b->fail(st, "system " + std::to_string(i) + ": " + ctx->err);
-    BATCH_TRY(hipEventRecord(b->joins[i], ctx->stream), "batch join");
-    BATCH_TRY(hipStreamWaitEvent(b->root, b->joins[i], 0), "batch join");
-  }
-  return MAHI_OK;
-}
-
 void batch_drop_graph(mahi_batch *b) {
   if (b->exec) (void)hipGraphExecDestroy(b->exec);
   if (b->graph) (void)hipGraphDestroy(b->graph);
@@ -506,6 +514,212 @@ bool same_args(const mahi_eval_args &a, const mahi_eval_args &c) {
   return a.xyz == c.xyz && a.energy == c.energy && a.forces == c.forces && a.dvdl == c.dvdl &&
          a.potential == c.potential && a.flags == c.flags && a.dedq == c.dedq && a.energy_qi == c.energy_qi &&
          a.dvdl_qi == c.dvdl_qi;
+}
+
+// Whether a batch can run packed: float32, periodic, one order of at most 8
+// (the 16x16x4 M2L kernel), and sites whose work arrays fit in local memory at
+// the batch's largest site.
+bool packed_ok(const std::vector<mahi_ctx *> &c, int &maxa, int &maxf) {
+  maxa = 1;
+  maxf = 1;
+  for (const mahi_ctx *x : c) {
+    if (x->prec != 32 || !x->periodic || x->p != c[0]->p || x->p > 8 || x->d > 7) return false;
+    maxa = std::max(maxa, x->maxa);
+    maxf = std::max(maxf, x->maxf);
+  }
+  return site_in_lds(c[0]->p, maxa, maxf);
+}
+
+#define PACK_TRY(expr, what)                                                             \
+  do {                                                                                   \
+    hipError_t _e = (expr);                                                              \
+    if (_e != hipSuccess) return std::string(what) + ": " + hip_msg(_e);                 \
+  } while (0)
+
+// Allocate the packed batch's buffers and block ranges and fill the
+// descriptor template (offsets, tables, plans); "" on success.
+std::string packed_setup(mahi_batch *b, int maxa, int maxf) {
+  const auto &c = b->ctxs;
+  const int ns = (int)c.size(), p = c[0]->p, K = ncoef(p), KS = c[0]->KS;
+  PackedPlan &pp = b->pp;
+  pp.nsys = ns;
+  pp.p = p;
+  pp.K = K;
+  pp.KS = KS;
+  int64_t atoms = 0, boxes = 0;
+  int leaves = 0, tiles = 0;
+  b->sys_host.assign(ns, PackedSys{});
+  for (int i = 0; i < ns; ++i) {
+    PackedSys &S = b->sys_host[i];
+    const mahi_ctx *x = c[i];
+    S.atom_off = atoms;
+    S.n_atoms = x->N;
+    S.box_off = boxes;
+    S.leaf_off = leaves;
+    S.d = x->d;
+    S.nleaf = 1 << (3 * x->d);
+    S.n_sites = x->M;
+    S.ke = x->ke;
+    atoms += x->N;
+    boxes += level_offset(x->d + 1);
+    leaves += S.nleaf;
+    tiles += x->plan32.ntiles;
+    pp.dmax = std::max(pp.dmax, x->d);
+  }
+  if (atoms > (int64_t)0x7fffffff - 1) return "the batch holds more than 2^31 - 2 atoms";
+  pp.n_atoms = atoms;
+  pp.nleaf = leaves;
+  pp.nbox = boxes + 1;  // + the all-zero row
+  // operator ranges: the fluid makespan model of the single-system plan on the batch's tiles
+  {
+    const double slots = 2.0 * (c[0]->n_cu > 0 ? c[0]->n_cu : 256), work = (double)tiles * kListLen;
+    double best = 1e300;
+    pp.nsplit = 1;
+    for (int sp = 1; sp <= kM2LMaxSplit; ++sp) {
+      const double item = (double)kListLen / sp;
+      const double cost = std::max(work / slots + 0.5 * item, item) + kListLen / 32.0 * sp;
+      if (cost < best - 1e-9) {
+        best = cost;
+        pp.nsplit = sp;
+      }
+    }
+  }
+  int chunk = (int)(16384 / (K * sizeof(float)));
+  pp.chunk = std::max(1, std::min(chunk, 32));
+  const int np_up = updown_np<float>(KS, true), np_dn = updown_np<float>(KS, false);
+  // block ranges of every per-system stage
+  std::vector<std::vector<int>> firsts;
+  auto stage = [&](PackedStage &stg, auto blocks_of) {
+    std::vector<int> f(ns + 1, 0);
+    for (int i = 0; i < ns; ++i) f[i + 1] = f[i] + blocks_of(i);
+    stg.blocks = f[ns];
+    firsts.push_back(std::move(f));
+  };
+  std::vector<PackedStage *> stages;
+  stage(pp.atoms, [&](int i) { return (int)((c[i]->N + 255) / 256); });
+  stages.push_back(&pp.atoms);
+  stage(pp.leaves, [&](int i) { return b->sys_host[i].nleaf; });
+  stages.push_back(&pp.leaves);
+  stage(pp.m2l, [&](int i) { return c[i]->plan32.ntiles * pp.nsplit; });
+  stages.push_back(&pp.m2l);
+  stage(pp.sites, [&](int i) { return c[i]->M; });
+  stages.push_back(&pp.sites);
+  for (int j = 1; j <= pp.dmax; ++j) {
+    stage(pp.up[j - 1], [&](int i) {
+      const int pl = c[i]->d - j;
+      return pl < 0 ? 0 : (int)(((int64_t(1) << (3 * pl)) + np_up - 1) / np_up);
+    });
+    stages.push_back(&pp.up[j - 1]);
+    stage(pp.down[j - 1], [&](int i) {
+      return j > c[i]->d ? 0 : (int)(((int64_t(1) << (3 * (j - 1))) + np_dn - 1) / np_dn);
+    });
+    stages.push_back(&pp.down[j - 1]);
+  }
+  int *firsts_dev = nullptr;
+  PACK_TRY(b->alloc(firsts_dev, sizeof(int) * (ns + 1) * firsts.size()), "alloc block ranges");
+  for (size_t k = 0; k < firsts.size(); ++k) {
+    PACK_TRY(hipMemcpy(firsts_dev + k * (ns + 1), firsts[k].data(), sizeof(int) * (ns + 1), hipMemcpyHostToDevice),
+             "upload block ranges");
+    stages[k]->first = firsts_dev + k * (ns + 1);
+  }
+  // buffers
+  const size_t N = (size_t)atoms, L = (size_t)leaves, B = (size_t)pp.nbox;
+  PACK_TRY(b->alloc(pp.key, sizeof(int) * N), "alloc keys");
+  PACK_TRY(b->alloc(pp.rank, sizeof(int) * N), "alloc ranks");
+  PACK_TRY(b->alloc(pp.tmp, sizeof(int) * N), "alloc scatter");
+  PACK_TRY(b->alloc(pp.perm, sizeof(int) * N), "alloc perm");
+  PACK_TRY(b->alloc(pp.slot_of, sizeof(int) * N), "alloc slot map");
+  PACK_TRY(b->alloc(pp.count, sizeof(int) * L), "alloc counts");
+  PACK_TRY(hipMemset(pp.count, 0, sizeof(int) * L), "zero counts");  // k_scan clears them after each use
+  PACK_TRY(b->alloc(pp.start, sizeof(int) * (L + 1)), "alloc starts");
+  PACK_TRY(b->alloc(pp.packed, sizeof(Atom4<float>) * N), "alloc packed atoms");
+  PACK_TRY(b->alloc(pp.sorted, sizeof(Atom4<float>) * N), "alloc sorted atoms");
+  PACK_TRY(b->alloc(pp.phi_sorted, sizeof(float) * N), "alloc potentials");
+  PACK_TRY(b->alloc(pp.Mc, sizeof(float) * B * KS), "alloc multipoles");
+  PACK_TRY(b->alloc(pp.Lc, sizeof(float) * B * KS), "alloc locals");
+  PACK_TRY(b->alloc(pp.part, sizeof(float) * pp.nsplit * B * KS), "alloc M2L partials");
+  // pads, level-0 partials and the zero row stay zero (never written)
+  PACK_TRY(hipMemset(pp.Mc, 0, sizeof(float) * B * KS), "zero multipoles");
+  PACK_TRY(hipMemset(pp.Lc, 0, sizeof(float) * B * KS), "zero locals");
+  PACK_TRY(hipMemset(pp.part, 0, sizeof(float) * pp.nsplit * B * KS), "zero partials");
+  PACK_TRY(b->alloc(pp.qds, sizeof(double) * 5 * L), "alloc moments");
+  PACK_TRY(b->alloc(pp.epart, sizeof(double) * L), "alloc energy partials");
+  PACK_TRY(b->alloc(b->sys_dev, sizeof(PackedSys) * ns), "alloc descriptors");
+  pp.sys = b->sys_dev;
+  // tables of the first context (one order: the same tables for every system)
+  pp.m2l_tab = static_cast<const float *>(c[0]->m2l);
+  pp.m2m = static_cast<const float *>(c[0]->m2m);
+  pp.l2l = static_cast<const float *>(c[0]->l2l);
+  pp.lists = c[0]->lists;
+  pp.LamT = c[0]->LamT;
+  const int site_dloc = site_lds_bytes(p, maxa, maxf, true) + kSiteStaticLds <= 65536 ? 1 : 0;
+  pp.site_lds = site_lds_bytes(p, maxa, maxf, site_dloc != 0);
+  for (int i = 0; i < ns; ++i) {
+    PackedSys &S = b->sys_host[i];
+    mahi_ctx *x = c[i];
+    S.qt = static_cast<const float *>(x->qt);
+    S.geom = x->geom;
+    S.site = site_args<float>(x);
+    S.site.maxa = maxa;
+    S.site.maxf = maxf;
+    S.site.dloc = site_dloc;
+    S.plan = x->plan32;
+    S.plan.tile0 = 0;
+    S.plan.tile_run = x->plan32.ntiles;
+    S.plan.nsplit = pp.nsplit;
+    S.plan.nbox = pp.nbox;                 // stride of the partial arrays
+    S.plan.zbox = boxes - S.box_off;       // the batch's zero row, relative to the system
+    S.p2p.d = x->d;
+    S.p2p.periodic = 1;
+    S.p2p.p = p;
+    S.p2p.K = K;
+    S.p2p.KS = KS;
+    S.p2p.cap = 0;
+    S.p2p.dloc = (size_t)4 * K * sizeof(float) <= 16384 ? 1 : 0;
+    S.p2p.ke = x->ke;
+  }
+  return "";
+}
+
+// Point the device descriptors at this call's arguments (waits for the
+// batch's stream first: a previous launch may still read them).
+mahi_status packed_table(mahi_batch *b, const mahi_eval_args *args) {
+  const size_t ns = b->ctxs.size();
+  bool same = b->table.size() == ns;
+  for (size_t i = 0; same && i < ns; ++i) same = same_args(args[i], b->table[i]);
+  if (same) return MAHI_OK;
+  for (size_t i = 0; i < ns; ++i) {
+    PackedSys &S = b->sys_host[i];
+    mahi_ctx *x = b->ctxs[i];
+    const mahi_eval_args &a = args[i];
+    S.xyz = static_cast<const float *>(a.xyz);
+    S.F = static_cast<float *>(a.forces);
+    S.pot = static_cast<float *>(a.potential);
+    S.E = a.energy ? a.energy : x->E;
+    S.E_qi = a.energy_qi;
+    S.io = SiteIO<float>{b->pp.phi_sorted, nullptr, S.F, (x->M > 0 && a.dvdl) ? a.dvdl : x->dvdl, x->dE_site,
+                         x->M > 0 ? a.dedq : nullptr, x->M > 0 ? a.dvdl_qi : nullptr, nullptr, 0};
+  }
+  BATCH_TRY(hipStreamSynchronize(b->root), "batch stream");
+  BATCH_TRY(hipMemcpy(b->sys_dev, b->sys_host.data(), sizeof(PackedSys) * ns, hipMemcpyHostToDevice),
+            "upload descriptors");
+  b->table.assign(args, args + ns);
+  batch_drop_graph(b);
+  return MAHI_OK;
+}
+
+// Fork from the origin stream into every context's stream, evaluate, join back.
+mahi_status batch_issue(mahi_batch *b, const mahi_eval_args *args) {
+  BATCH_TRY(hipEventRecord(b->fork, b->root), "batch fork");
+  for (size_t i = 0; i < b->ctxs.size(); ++i) {
+    mahi_ctx *ctx = b->ctxs[i];
+    BATCH_TRY(hipStreamWaitEvent(ctx->stream, b->fork, 0), "batch fork");
+    const mahi_status st = ctx->prec == 32 ? eval_impl<float>(ctx, &args[i]) : eval_impl<double>(ctx, &args[i]);
+    if (st != MAHI_OK) return b->fail(st, "system " + std::to_string(i) + ": " + ctx->err);
+    BATCH_TRY(hipEventRecord(b->joins[i], ctx->stream), "batch join");
+    BATCH_TRY(hipStreamWaitEvent(b->root, b->joins[i], 0), "batch join");
+  }
+  return MAHI_OK;
 }
 
 void free_ctx(mahi_ctx *ctx) {
@@ -914,7 +1128,7 @@ mahi_status mahi_debug_copy(mahi_ctx *ctx, int which, void *host_out, int64_t co
   return MAHI_OK;
 }
 
-mahi_status mahi_batch_create(mahi_batch **out, mahi_ctx *const *ctxs, int n_ctx, int use_graph, void *hip_stream) {
+mahi_status mahi_batch_create(mahi_batch **out, mahi_ctx *const *ctxs, int n_ctx, int flags, void *hip_stream) {
   g_create_error.clear();
   if (!out) return MAHI_EINVAL;
   *out = nullptr;
@@ -922,10 +1136,11 @@ mahi_status mahi_batch_create(mahi_batch **out, mahi_ctx *const *ctxs, int n_ctx
     g_create_error = "ctxs must hold at least one context";
     return MAHI_EINVAL;
   }
-  if (use_graph != 0 && use_graph != 1) {
-    g_create_error = "use_graph must be 0 or 1";
+  if (flags & ~(int)(MAHI_BATCH_GRAPH | MAHI_BATCH_PACKED)) {
+    g_create_error = "unknown batch flags";
     return MAHI_EINVAL;
   }
+  const bool want_graph = (flags & MAHI_BATCH_GRAPH) != 0, want_packed = (flags & MAHI_BATCH_PACKED) != 0;
   for (int i = 0; i < n_ctx; ++i) {
     if (!ctxs[i]) {
       g_create_error = "NULL context";
@@ -941,17 +1156,24 @@ mahi_status mahi_batch_create(mahi_batch **out, mahi_ctx *const *ctxs, int n_ctx
       return MAHI_EINVAL;
     }
   }
-  if (use_graph) {
-    // The captured-graph path ended in a host segmentation fault on its first
-    // capture and launch, with no cause shown yet; it stays off until one is.
-    g_create_error = "graph capture of a batch is disabled in this build (use_graph = 0 evaluates eagerly)";
+  if (want_graph && !want_packed) {
+    // The fork/join of separate contexts is not captured: its first capture
+    // and launch ended in a host segmentation fault whose cause is not shown.
+    g_create_error = "graph capture needs a packed batch (MAHI_BATCH_PACKED)";
+    return MAHI_EUNSUPPORTED;
+  }
+  int maxa = 1, maxf = 1;
+  if (want_packed && !packed_ok(std::vector<mahi_ctx *>(ctxs, ctxs + n_ctx), maxa, maxf)) {
+    g_create_error = "a packed batch needs float32 periodic contexts of one order (at most 8) whose sites fit in "
+                     "local memory";
     return MAHI_EUNSUPPORTED;
   }
   mahi_batch *b = new (std::nothrow) mahi_batch;
   if (!b) return MAHI_ENOMEM;
   b->ctxs.assign(ctxs, ctxs + n_ctx);
   b->device = ctxs[0]->device;
-  b->use_graph = use_graph != 0;
+  b->use_graph = want_graph;
+  b->packed = want_packed;
   auto bad = [&](const char *m) {
     g_create_error = m;
     mahi_batch_destroy(b);
@@ -968,6 +1190,14 @@ mahi_status mahi_batch_create(mahi_batch **out, mahi_ctx *const *ctxs, int n_ctx
   b->joins.assign(n_ctx, nullptr);
   for (auto &e : b->joins)
     if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) return bad("event creation failed");
+  if (b->packed) {
+    const std::string e = packed_setup(b, maxa, maxf);
+    if (!e.empty()) {
+      g_create_error = e;
+      mahi_batch_destroy(b);
+      return MAHI_EDEVICE;
+    }
+  }
   *out = b;
   return MAHI_OK;
 }
@@ -983,6 +1213,35 @@ mahi_status mahi_batch_eval(mahi_batch *b, const mahi_eval_args *args) {
     if (ctx->prof_max > 0) return b->fail(MAHI_ESTATE, "system " + std::to_string(i) + ": stage profiling is open");
   }
   BATCH_TRY(hipSetDevice(b->device), "set device");
+  if (b->packed) {
+    const mahi_status st = packed_table(b, args);
+    if (st != MAHI_OK) return st;
+    if (!b->use_graph) {
+      launch_packed(b->pp, b->root);
+      BATCH_TRY(hipGetLastError(), "packed launch");
+      return MAHI_OK;
+    }
+    if (!b->exec) {
+      // one stream, kernel launches only: capture them once per set of arguments
+      BATCH_TRY(hipStreamBeginCapture(b->root, hipStreamCaptureModeThreadLocal), "begin capture");
+      launch_packed(b->pp, b->root);
+      const hipError_t el = hipGetLastError();
+      hipGraph_t g = nullptr;
+      const hipError_t e = hipStreamEndCapture(b->root, &g);
+      if (el != hipSuccess || e != hipSuccess) {
+        if (g) (void)hipGraphDestroy(g);
+        return b->fail(MAHI_EDEVICE, std::string("capture: ") + hip_msg(el != hipSuccess ? el : e));
+      }
+      b->graph = g;
+      const hipError_t ei = hipGraphInstantiate(&b->exec, g, nullptr, nullptr, 0);
+      if (ei != hipSuccess) {
+        batch_drop_graph(b);
+        return b->fail(MAHI_EDEVICE, std::string("graph instantiate: ") + hip_msg(ei));
+      }
+    }
+    BATCH_TRY(hipGraphLaunch(b->exec, b->root), "graph launch");
+    return MAHI_OK;
+  }
   if (!b->use_graph) return batch_issue(b, args);
   bool same = b->exec != nullptr && b->captured.size() == b->ctxs.size();
   for (size_t i = 0; same && i < b->ctxs.size(); ++i) same = same_args(args[i], b->captured[i]);
@@ -1014,6 +1273,7 @@ void mahi_batch_destroy(mahi_batch *b) {
   (void)hipSetDevice(b->device);
   if (b->root) (void)hipStreamSynchronize(b->root);
   batch_drop_graph(b);
+  for (auto &d : b->bufs) (void)hipFree(d.p);
   if (b->fork) (void)hipEventDestroy(b->fork);
   for (auto &e : b->joins)
     if (e) (void)hipEventDestroy(e);

@@ -273,17 +273,21 @@ __device__ __forceinline__ void locate(const T *xyz, int64_t i, const Geom &g, i
 // equal keys is fixed later by k_leafsort) and its packed leaf-local
 // coordinates (leaf units, centred) with the scaled charge.  Consecutive
 // atoms that fall in one leaf take their ranks with a single atomic.
+// Block bid of nblk (several systems of a batch each bin their own atoms;
+// their keys are offset by key_off, the system's first leaf in the batch).
 template <class T>
-__global__ void k_bin(const T *__restrict__ xyz, const T *__restrict__ qt, int64_t n_atoms,
-                      const Geom *__restrict__ gp, int d, int periodic, int *__restrict__ key, int *__restrict__ rank,
-                      int *__restrict__ count, Atom4<T> *__restrict__ packed) {
+__device__ __forceinline__ void bin_body(const T *__restrict__ xyz, const T *__restrict__ qt, int64_t n_atoms,
+                                         const Geom *__restrict__ gp, int d, int periodic, int *__restrict__ key,
+                                         int key_off, int *__restrict__ rank, int *__restrict__ count,
+                                         Atom4<T> *__restrict__ packed, Atom4<T> *__restrict__ packed_lo, int bid,
+                                         int nblk) {
   const Geom g = *gp;
   const int n = 1 << d;
   const double inv_h = n / g.edge;
   const int lane = threadIdx.x & 63;
-  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  const int64_t stride = (int64_t)nblk * blockDim.x;
   // whole waves step together (the loop bound is the same for every lane)
-  for (int64_t i0 = blockIdx.x * (int64_t)blockDim.x + (threadIdx.x - lane); i0 < n_atoms; i0 += stride) {
+  for (int64_t i0 = bid * (int64_t)blockDim.x + (threadIdx.x - lane); i0 < n_atoms; i0 += stride) {
     const int64_t i = i0 + lane;
     const bool valid = i < n_atoms;
     int k = -1;
@@ -292,13 +296,15 @@ __global__ void k_bin(const T *__restrict__ xyz, const T *__restrict__ qt, int64
       int c[3];
       locate(xyz, i, g, periodic, n, w, c);
       k = (int)morton(c[0], c[1], c[2]);
-      key[i] = k;
+      key[i] = k + key_off;
       Atom4<T> at;
-      at.x = (T)(w[0] * inv_h - (c[0] + 0.5));
-      at.y = (T)(w[1] * inv_h - (c[1] + 0.5));
-      at.z = (T)(w[2] * inv_h - (c[2] + 0.5));
+      const double lx = w[0] * inv_h - (c[0] + 0.5), ly = w[1] * inv_h - (c[1] + 0.5), lz = w[2] * inv_h - (c[2] + 0.5);
+      at.x = (T)lx;
+      at.y = (T)ly;
+      at.z = (T)lz;
       at.q = qt[i];
       packed[i] = at;
+      if (packed_lo) packed_lo[i] = Atom4<T>{(T)(lx - (double)at.x), (T)(ly - (double)at.y), (T)(lz - (double)at.z), T(0)};
     }
     // a run of equal keys on consecutive lanes (the atoms of one molecule)
     // reserves its ranks with one atomic by its first lane
@@ -313,6 +319,13 @@ __global__ void k_bin(const T *__restrict__ xyz, const T *__restrict__ qt, int64
     base = __shfl(base, h, 64);
     if (valid) rank[i] = base + (lane - h);
   }
+}
+
+template <class T>
+__global__ void k_bin(const T *__restrict__ xyz, const T *__restrict__ qt, int64_t n_atoms,
+                      const Geom *__restrict__ gp, int d, int periodic, int *__restrict__ key, int *__restrict__ rank,
+                      int *__restrict__ count, Atom4<T> *__restrict__ packed, Atom4<T> *__restrict__ packed_lo) {
+  bin_body<T>(xyz, qt, n_atoms, gp, d, periodic, key, 0, rank, count, packed, packed_lo, blockIdx.x, gridDim.x);
 }
 
 // Exclusive prefix sum of the leaf counts in one block: thread t owns 32
@@ -407,7 +420,9 @@ __global__ void k_scatter(const int *__restrict__ key, const int *__restrict__ r
 template <class T>
 __global__ void __launch_bounds__(256) k_leafsort(const int *__restrict__ tmp, const int *__restrict__ start, int nleaf,
                                                   const Atom4<T> *__restrict__ packed, int *__restrict__ perm,
-                                                  int *__restrict__ slot_of, Atom4<T> *__restrict__ sorted) {
+                                                  int *__restrict__ slot_of, Atom4<T> *__restrict__ sorted,
+                                                  const Atom4<T> *__restrict__ packed_lo,
+                                                  Atom4<T> *__restrict__ sorted_lo) {
   const int leaf = blockIdx.x * 4 + (threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
   if (leaf >= nleaf) return;
@@ -425,6 +440,7 @@ __global__ void __launch_bounds__(256) k_leafsort(const int *__restrict__ tmp, c
     perm[slot] = me;
     slot_of[me] = slot;
     sorted[slot] = packed[me];
+    if (sorted_lo) sorted_lo[slot] = packed_lo[me];
   }
 }
 
@@ -432,12 +448,12 @@ __global__ void __launch_bounds__(256) k_leafsort(const int *__restrict__ tmp, c
 // P2M: leaf multipoles; also the float64 charge moments for the lattice
 // ---------------------------------------------------------------------------
 template <class T, int PT>
-__global__ void __launch_bounds__(64) k_p2m(const Atom4<T> *__restrict__ sorted, const int *__restrict__ start,
-                                            int p, int K, int KS, int chunk, T *__restrict__ Mleaf, double *__restrict__ qds,
-                                            const Geom *__restrict__ gp, int d) {
+__device__ __forceinline__ void p2m_body(const Atom4<T> *__restrict__ sorted, const int *__restrict__ start, int p,
+                                         int K, int KS, int chunk, T *__restrict__ Mleaf, double *__restrict__ qds,
+                                         const Geom *__restrict__ gp, int d, int leaf) {
   extern __shared__ unsigned char smem_raw[];
   T *rows = reinterpret_cast<T *>(smem_raw);
-  const int leaf = blockIdx.x, lane = threadIdx.x;
+  const int lane = threadIdx.x;
   const int s0 = start[leaf], cnt = start[leaf + 1] - s0;
   constexpr int kMaxPer = ((kMaxOrder + 1) * (kMaxOrder + 1) + 63) / 64;
   // float32: compensated sums (Knuth's two-sum, error terms in cmp).  A leaf's
@@ -511,6 +527,13 @@ __global__ void __launch_bounds__(64) k_p2m(const Atom4<T> *__restrict__ sorted,
   }
 }
 
+template <class T, int PT>
+__global__ void __launch_bounds__(64) k_p2m(const Atom4<T> *__restrict__ sorted, const int *__restrict__ start,
+                                            int p, int K, int KS, int chunk, T *__restrict__ Mleaf, double *__restrict__ qds,
+                                            const Geom *__restrict__ gp, int d) {
+  p2m_body<T, PT>(sorted, start, p, K, KS, chunk, Mleaf, qds, gp, d, blockIdx.x);
+}
+
 // ---------------------------------------------------------------------------
 // Charge moments Q, D, S2 of the lattice remainder, first stage: block b sums
 // the per-leaf moments of leaves b*256 + t, stepping over all blocks, then its
@@ -539,9 +562,9 @@ __global__ void __launch_bounds__(256) k_moments(const double *__restrict__ qds,
 // (summed from nleaf rows of five moments: the block partials of k_moments).
 // ---------------------------------------------------------------------------
 template <class T>
-__global__ void __launch_bounds__(1024) k_lattice(const T *__restrict__ M, T *__restrict__ L,
-                                                  const double *__restrict__ LamT, int K,
-                                                  const double *__restrict__ qds, int nleaf, Geom *g) {
+__device__ __forceinline__ void lattice_body(const T *__restrict__ M, T *__restrict__ L,
+                                             const double *__restrict__ LamT, int K, const double *__restrict__ qds,
+                                             int nleaf, Geom *g) {
   __shared__ double red[5][1024];
   __shared__ double mroot[(kMaxOrder + 1) * (kMaxOrder + 1)];
   __shared__ double rowp[4][(kMaxOrder + 1) * (kMaxOrder + 1)];
@@ -576,7 +599,12 @@ __global__ void __launch_bounds__(1024) k_lattice(const T *__restrict__ M, T *__
     g->D[1] = red[2][0];
     g->D[2] = red[3][0];
     g->S2 = red[4][0];
+    // the root monopole is the total charge: take the float64 sum (in float32
+    // the root multipole carries the rounding of every level's sums, which the
+    // lattice operator would turn into a constant potential offset)
+    mroot[0] = red[0][0];
   }
+  __syncthreads();
   // root local = Lambda M_root: row r, column quarter q in thread (q, r); quarters summed in order
   const int q = t >> 8;
   for (int r = t & 255; r < K; r += 256) {
@@ -587,6 +615,13 @@ __global__ void __launch_bounds__(1024) k_lattice(const T *__restrict__ M, T *__
   }
   __syncthreads();
   for (int rr = t; rr < K; rr += 1024) L[rr] = (T)(((rowp[0][rr] + rowp[1][rr]) + rowp[2][rr]) + rowp[3][rr]);
+}
+
+template <class T>
+__global__ void __launch_bounds__(1024) k_lattice(const T *__restrict__ M, T *__restrict__ L,
+                                                  const double *__restrict__ LamT, int K,
+                                                  const double *__restrict__ qds, int nleaf, Geom *g) {
+  lattice_body<T>(M, L, LamT, K, qds, nleaf, g);
 }
 
 // ---------------------------------------------------------------------------
@@ -824,14 +859,14 @@ __global__ void __launch_bounds__(64 * TPT) k_xlate(const T *X, T *Y, const T *_
 // result to the child's local expansion in place (one writer per element).
 // ---------------------------------------------------------------------------
 template <class T, bool UP, int NP>
-__global__ void __launch_bounds__(1024) k_updown(T *__restrict__ X, const T *__restrict__ A, int K, int KS,
-                                                 int64_t off_parent, int64_t off_child, int64_t nparent) {
+__device__ __forceinline__ void updown_body(T *__restrict__ X, const T *__restrict__ A, int K, int KS,
+                                            int64_t off_parent, int64_t off_child, int64_t nparent, int bid) {
   extern __shared__ unsigned char smem_raw[];
   // inputs transposed so that the NP parents of one (c, k) are contiguous:
   //   UP: xs[c][k][NP] (children);  down: xs[k][NP] (parents)
   T *xs = reinterpret_cast<T *>(smem_raw);
   T *part = xs + (size_t)(UP ? 8 : 1) * KS * NP;  // UP: [NP][8][KS] child partials
-  const int64_t P0 = (int64_t)blockIdx.x * NP;
+  const int64_t P0 = (int64_t)bid * NP;
   const int np = (int)min((int64_t)NP, nparent - P0);
   const int in_len = UP ? 8 * KS : KS;
   {
@@ -882,6 +917,12 @@ __global__ void __launch_bounds__(1024) k_updown(T *__restrict__ X, const T *__r
       if (r < K) X[(off_parent + P0 + p) * KS + r] = s;
     }
   }
+}
+
+template <class T, bool UP, int NP>
+__global__ void __launch_bounds__(1024) k_updown(T *__restrict__ X, const T *__restrict__ A, int K, int KS,
+                                                 int64_t off_parent, int64_t off_child, int64_t nparent) {
+  updown_body<T, UP, NP>(X, A, K, KS, off_parent, off_child, nparent, blockIdx.x);
 }
 
 // Matrix-core tile check: C[rows x 64] = A[rows x kk] * B[kk x 64] with the same
@@ -951,12 +992,24 @@ __device__ __forceinline__ P2PPass p2p_pass_shape(int nt, int &M) {
 }
 
 // FIELD = false: potential only (evaluations that return no forces).
-template <class T, int M, bool SELF, bool FIELD>
-__device__ __forceinline__ void p2p_pair(const Atom4<T> &o, const T (&px)[M], const T (&py)[M], const T (&pz)[M],
+// LO: the pair displacement from the leading parts and the rounding residuals
+// of both positions, (p - o) + (p_lo - o_lo).  The leading difference of two
+// nearby atoms is exact, so the displacement keeps float32 precision relative
+// to its own length instead of to the leaf edge (float32 leaf-local positions
+// alone carry ~2e-8 nm, which dominates the force error of close pairs once
+// the expansions are accurate to order 16).
+template <class T, int M, bool SELF, bool FIELD, bool LO>
+__device__ __forceinline__ void p2p_pair(const Atom4<T> &o, const Atom4<T> &ol, const T (&px)[M], const T (&py)[M],
+                                         const T (&pz)[M], const T (&pxl)[M], const T (&pyl)[M], const T (&pzl)[M],
                                          T (&phi)[M], T (&ex)[M], T (&ey)[M], T (&ez)[M]) {
 #pragma unroll
   for (int m = 0; m < M; ++m) {
-    const T rx = px[m] - o.x, ry = py[m] - o.y, rz = pz[m] - o.z;
+    T rx = px[m] - o.x, ry = py[m] - o.y, rz = pz[m] - o.z;
+    if constexpr (LO) {
+      rx += pxl[m] - ol.x;
+      ry += pyl[m] - ol.y;
+      rz += pzl[m] - ol.z;
+    }
     const T r2 = rx * rx + ry * ry + rz * rz;
     T ri = rsqrt_t<T>(r2);
     if (SELF) ri = r2 > T(0) ? ri : T(0);
@@ -972,23 +1025,33 @@ __device__ __forceinline__ void p2p_pair(const Atom4<T> &o, const T (&px)[M], co
 }
 
 // Sources s[g], s[g + G], ... of one neighbour leaf (cnt atoms), with the next
-// two loaded before the current two are used.
-template <class T, int M, bool SELF, bool FIELD>
-__device__ __forceinline__ void p2p_run(const Atom4<T> *__restrict__ s, int cnt, int g, int G, const T (&px)[M],
-                                        const T (&py)[M], const T (&pz)[M], T (&phi)[M], T (&ex)[M], T (&ey)[M],
-                                        T (&ez)[M]) {
+// two loaded before the current two are used (LO: with their residuals sl).
+template <class T, int M, bool SELF, bool FIELD, bool LO>
+__device__ __forceinline__ void p2p_run(const Atom4<T> *__restrict__ s, const Atom4<T> *__restrict__ sl, int cnt,
+                                        int g, int G, const T (&px)[M], const T (&py)[M], const T (&pz)[M],
+                                        const T (&pxl)[M], const T (&pyl)[M], const T (&pzl)[M], T (&phi)[M],
+                                        T (&ex)[M], T (&ey)[M], T (&ez)[M]) {
   int j = g;
   if (j >= cnt) return;
   const int last = cnt - 1;
+  const Atom4<T> zero{T(0), T(0), T(0), T(0)};
   Atom4<T> o0 = s[j], o1 = s[min(j + G, last)];
+  Atom4<T> l0 = LO ? sl[j] : zero, l1 = LO ? sl[min(j + G, last)] : zero;
   for (; j + G < cnt; j += 2 * G) {
     const Atom4<T> n0 = s[min(j + 2 * G, last)], n1 = s[min(j + 3 * G, last)];
-    p2p_pair<T, M, SELF, FIELD>(o0, px, py, pz, phi, ex, ey, ez);
-    p2p_pair<T, M, SELF, FIELD>(o1, px, py, pz, phi, ex, ey, ez);
+    Atom4<T> m0 = zero, m1 = zero;
+    if constexpr (LO) {
+      m0 = sl[min(j + 2 * G, last)];
+      m1 = sl[min(j + 3 * G, last)];
+    }
+    p2p_pair<T, M, SELF, FIELD, LO>(o0, l0, px, py, pz, pxl, pyl, pzl, phi, ex, ey, ez);
+    p2p_pair<T, M, SELF, FIELD, LO>(o1, l1, px, py, pz, pxl, pyl, pzl, phi, ex, ey, ez);
     o0 = n0;
     o1 = n1;
+    l0 = m0;
+    l1 = m1;
   }
-  if (j < cnt) p2p_pair<T, M, SELF, FIELD>(o0, px, py, pz, phi, ex, ey, ez);
+  if (j < cnt) p2p_pair<T, M, SELF, FIELD, LO>(o0, l0, px, py, pz, pxl, pyl, pzl, phi, ex, ey, ez);
 }
 
 template <class T>
@@ -999,19 +1062,26 @@ __device__ __forceinline__ T shfl_t(T v, int src) {
 // One pass: targets [tp, tp + nt) (nt <= 64) against the 27 neighbour leaves
 // (start and count per neighbour in nb_st / nb_ct).  Lane u < nt receives the
 // sums for target u (leaf units) in acc.
-template <class T, int M, bool FIELD>
-__device__ __forceinline__ void p2p_wave(const Atom4<T> *__restrict__ sorted, const int *nb_st, const int *nb_ct,
-                                         int tp, int nt, int lane, P2PPass ps, T (&acc)[4]) {
+template <class T, int M, bool FIELD, bool LO>
+__device__ __forceinline__ void p2p_wave(const Atom4<T> *__restrict__ sorted, const Atom4<T> *__restrict__ sorted_lo,
+                                         const int *nb_st, const int *nb_ct, int tp, int nt, int lane, P2PPass ps,
+                                         T (&acc)[4]) {
   const int p = lane % ps.P, g = lane / ps.P;
-  T qx[M], qy[M], qz[M], phi[M], ex[M], ey[M], ez[M];
+  T qx[M], qy[M], qz[M], qxl[M], qyl[M], qzl[M], phi[M], ex[M], ey[M], ez[M];
 #pragma unroll
   for (int m = 0; m < M; ++m) {
     const int u = p + m * ps.P;
-    Atom4<T> me = {T(0), T(0), T(0), T(0)};
-    if (u < nt) me = sorted[tp + u];
+    Atom4<T> me = {T(0), T(0), T(0), T(0)}, ml = {T(0), T(0), T(0), T(0)};
+    if (u < nt) {
+      me = sorted[tp + u];
+      if constexpr (LO) ml = sorted_lo[tp + u];
+    }
     qx[m] = me.x;
     qy[m] = me.y;
     qz[m] = me.z;
+    qxl[m] = ml.x;
+    qyl[m] = ml.y;
+    qzl[m] = ml.z;
     phi[m] = ex[m] = ey[m] = ez[m] = T(0);
   }
   if (g < ps.G) {
@@ -1020,15 +1090,30 @@ __device__ __forceinline__ void p2p_wave(const Atom4<T> *__restrict__ sorted, co
       if (cnt == 0) continue;
       // target relative to the neighbour's centre: subtract the neighbour offset
       const T sx = (T)(r / 9 - 1), sy = (T)((r / 3) % 3 - 1), sz = (T)(r % 3 - 1);
-      T px[M], py[M], pz[M];
+      T px[M], py[M], pz[M], pxl[M], pyl[M], pzl[M];
 #pragma unroll
       for (int m = 0; m < M; ++m) {
         px[m] = qx[m] - sx;
         py[m] = qy[m] - sy;
         pz[m] = qz[m] - sz;
+        if constexpr (LO) {
+          // exact two-sum of the shift: p - s = px + (rounding error), plus the residual
+          T bp = px[m] - qx[m];
+          pxl[m] = ((qx[m] - (px[m] - bp)) + (-sx - bp)) + qxl[m];
+          bp = py[m] - qy[m];
+          pyl[m] = ((qy[m] - (py[m] - bp)) + (-sy - bp)) + qyl[m];
+          bp = pz[m] - qz[m];
+          pzl[m] = ((qz[m] - (pz[m] - bp)) + (-sz - bp)) + qzl[m];
+        } else {
+          pxl[m] = pyl[m] = pzl[m] = T(0);
+        }
       }
-      if (r == 13) p2p_run<T, M, true, FIELD>(sorted + nb_st[r], cnt, g, ps.G, px, py, pz, phi, ex, ey, ez);
-      else p2p_run<T, M, false, FIELD>(sorted + nb_st[r], cnt, g, ps.G, px, py, pz, phi, ex, ey, ez);
+      const Atom4<T> *sl = LO ? sorted_lo + nb_st[r] : nullptr;
+      if (r == 13)
+        p2p_run<T, M, true, FIELD, LO>(sorted + nb_st[r], sl, cnt, g, ps.G, px, py, pz, pxl, pyl, pzl, phi, ex, ey, ez);
+      else
+        p2p_run<T, M, false, FIELD, LO>(sorted + nb_st[r], sl, cnt, g, ps.G, px, py, pz, pxl, pyl, pzl, phi, ex, ey,
+                                        ez);
     }
   }
   // lane u (target u = p' + m' P) gathers its sums from lanes g P + p' in group order
@@ -1054,12 +1139,15 @@ __device__ __forceinline__ void p2p_wave(const Atom4<T> *__restrict__ sorted, co
   }
 }
 
-template <class T, int PT, bool FIELD>
-__global__ void __launch_bounds__(64) k_p2p_l2p(const Atom4<T> *__restrict__ sorted, const int *__restrict__ start,
-                                                const int *__restrict__ perm, const T *__restrict__ Lleaf,
-                                                const Geom *__restrict__ gp, P2PArgs a, T *__restrict__ phi_sorted,
-                                                T *__restrict__ F, T *__restrict__ pot_user,
-                                                double *__restrict__ epart) {
+// Block bid handles one leaf.  perm holds atom indices of the whole batch:
+// perm_off (the system's first atom) turns them into indices of F and pot_user.
+template <class T, int PT, bool FIELD, bool LO>
+__device__ __forceinline__ void p2p_body(const Atom4<T> *__restrict__ sorted, const Atom4<T> *__restrict__ sorted_lo,
+                                         const int *__restrict__ start,
+                                         const int *__restrict__ perm, int perm_off, const T *__restrict__ Lleaf,
+                                         const Geom *__restrict__ gp, const P2PArgs &a, T *__restrict__ phi_sorted,
+                                         T *__restrict__ F, T *__restrict__ pot_user, double *__restrict__ epart,
+                                         int bid) {
   extern __shared__ unsigned char smem_raw[];
   T *loc = reinterpret_cast<T *>(smem_raw);  // [KL]: L, then (dloc) Dx, Dy, Dz
   __shared__ int nb_st[27], nb_ct[27];
@@ -1067,7 +1155,6 @@ __global__ void __launch_bounds__(64) k_p2p_l2p(const Atom4<T> *__restrict__ sor
   const int lane = threadIdx.x;
   const int n = 1 << a.d;
   const int nleaf = n * n * n;
-  const int bid = blockIdx.x;
   const int leaf = nleaf >= 8 ? (bid & 7) * (nleaf >> 3) + (bid >> 3) : bid;
   int bx = 0, by = 0, bz = 0;
   unmorton((uint32_t)leaf, bx, by, bz);
@@ -1122,9 +1209,9 @@ __global__ void __launch_bounds__(64) k_p2p_l2p(const Atom4<T> *__restrict__ sor
     int M;
     const P2PPass ps = p2p_pass_shape(nt, M);
     T acc[4] = {T(0), T(0), T(0), T(0)};
-    if (M == 1) p2p_wave<T, 1, FIELD>(sorted, nb_st, nb_ct, tp, nt, lane, ps, acc);
-    else if (M == 2) p2p_wave<T, 2, FIELD>(sorted, nb_st, nb_ct, tp, nt, lane, ps, acc);
-    else p2p_wave<T, 3, FIELD>(sorted, nb_st, nb_ct, tp, nt, lane, ps, acc);
+    if (M == 1) p2p_wave<T, 1, FIELD, LO>(sorted, sorted_lo, nb_st, nb_ct, tp, nt, lane, ps, acc);
+    else if (M == 2) p2p_wave<T, 2, FIELD, LO>(sorted, sorted_lo, nb_st, nb_ct, tp, nt, lane, ps, acc);
+    else p2p_wave<T, 3, FIELD, LO>(sorted, sorted_lo, nb_st, nb_ct, tp, nt, lane, ps, acc);
     if (lane < nt) {
       const int ti = tp + lane;
       const Atom4<T> me = sorted[ti];
@@ -1183,7 +1270,7 @@ __global__ void __launch_bounds__(64) k_p2p_l2p(const Atom4<T> *__restrict__ sor
       }
       const double q = (double)me.q;
       phi_sorted[ti] = (T)ph;
-      const int64_t u = perm[ti];
+      const int64_t u = perm[ti] - perm_off;
       if (FIELD && F) {
         F[3 * u + 0] = (T)(a.ke * q * E[0]);
         F[3 * u + 1] = (T)(a.ke * q * E[1]);
@@ -1195,6 +1282,17 @@ __global__ void __launch_bounds__(64) k_p2p_l2p(const Atom4<T> *__restrict__ sor
   }
   for (int off = 32; off > 0; off >>= 1) esum += __shfl_xor(esum, off);
   if (lane == 0) epart[leaf] = esum;
+}
+
+template <class T, int PT, bool FIELD, bool LO>
+__global__ void __launch_bounds__(64) k_p2p_l2p(const Atom4<T> *__restrict__ sorted,
+                                                const Atom4<T> *__restrict__ sorted_lo, const int *__restrict__ start,
+                                                const int *__restrict__ perm, const T *__restrict__ Lleaf,
+                                                const Geom *__restrict__ gp, P2PArgs a, T *__restrict__ phi_sorted,
+                                                T *__restrict__ F, T *__restrict__ pot_user,
+                                                double *__restrict__ epart) {
+  p2p_body<T, PT, FIELD, LO>(sorted, sorted_lo, start, perm, 0, Lleaf, gp, a, phi_sorted, F, pot_user, epart,
+                             blockIdx.x);
 }
 
 // ---------------------------------------------------------------------------
@@ -1233,13 +1331,13 @@ __global__ void k_charge_scale(const int *__restrict__ atom_off, const int *__re
 //   dE_QI/dlt_r = ke sum_i q^r_i V_i     (charge interpolation: E_QI = ke/2 qt.Phi.qt)
 // ---------------------------------------------------------------------------
 template <class T, int PT, bool WS>
-__global__ void __launch_bounds__(256) k_site(SiteArgs a, const T *__restrict__ xyz, const int *__restrict__ slot_of,
-                                              const Geom *__restrict__ gp, const double *__restrict__ LamT,
-                                              SiteIO<T> io) {
+__device__ __forceinline__ void site_body(const SiteArgs &a, const T *__restrict__ xyz, const int *__restrict__ slot_of,
+                                          const Geom *__restrict__ gp, const double *__restrict__ LamT,
+                                          const SiteIO<T> &io, int s) {
   T *__restrict__ F = io.F;
   constexpr int NT = 256;
   extern __shared__ double sm_lds[];
-  const int s = blockIdx.x, tid = threadIdx.x;
+  const int tid = threadIdx.x;
   // work arrays in local memory, or (WS) this site's region of the global workspace;
   // a compile-time choice, so that the local-memory case keeps LDS instructions
   double *sm = WS ? io.ws + (size_t)s * io.ws_stride : sm_lds;
@@ -1468,11 +1566,18 @@ __global__ void __launch_bounds__(256) k_site(SiteArgs a, const T *__restrict__ 
   }
 }
 
+template <class T, int PT, bool WS>
+__global__ void __launch_bounds__(256) k_site(SiteArgs a, const T *__restrict__ xyz, const int *__restrict__ slot_of,
+                                              const Geom *__restrict__ gp, const double *__restrict__ LamT,
+                                              SiteIO<T> io) {
+  site_body<T, PT, WS>(a, xyz, slot_of, gp, LamT, io, blockIdx.x);
+}
+
 // E = ke (1/2 sum_blocks epart + sum_sites dE) and, when E_qi is set, the
 // charge-interpolated energy ke/2 sum_blocks epart; fixed order.
-__global__ void __launch_bounds__(1024) k_finalize(const double *__restrict__ epart, int nb,
-                                                   const double *__restrict__ dE_site, int ns, double ke,
-                                                   double *__restrict__ E, double *__restrict__ E_qi) {
+__device__ __forceinline__ void finalize_body(const double *__restrict__ epart, int nb,
+                                              const double *__restrict__ dE_site, int ns, double ke,
+                                              double *__restrict__ E, double *__restrict__ E_qi) {
   __shared__ double s[1024], sq[1024];
   const int t = threadIdx.x;
   // fixed-order partial sums: thread t adds entries t, t + 1024, ... (loads unrolled 8-fold)
@@ -1501,6 +1606,95 @@ __global__ void __launch_bounds__(1024) k_finalize(const double *__restrict__ ep
     *E = ke * s[0];
     if (E_qi) *E_qi = ke * sq[0];
   }
+}
+
+__global__ void __launch_bounds__(1024) k_finalize(const double *__restrict__ epart, int nb,
+                                                   const double *__restrict__ dE_site, int ns, double ke,
+                                                   double *__restrict__ E, double *__restrict__ E_qi) {
+  finalize_body(epart, nb, dE_site, ns, ke, E, E_qi);
+}
+
+// ---------------------------------------------------------------------------
+// Packed batch kernels: the single-system stages above, one launch over all
+// systems of a batch.  Each block finds its system by a binary search of the
+// stage's block ranges and runs the same body with that system's offsets.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int packed_system(const int *__restrict__ first, int nsys, int b) {
+  int lo = 0, hi = nsys;  // largest s with first[s] <= b (a system with blocks)
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (first[mid] <= b) lo = mid;
+    else hi = mid;
+  }
+  return lo;
+}
+
+__global__ void kp_bin(const PackedSys *__restrict__ sys, const int *__restrict__ first, int nsys,
+                       int *__restrict__ key, int *__restrict__ rank, int *__restrict__ count,
+                       Atom4<float> *__restrict__ packed) {
+  const int s = packed_system(first, nsys, blockIdx.x);
+  const PackedSys &S = sys[s];
+  bin_body<float>(S.xyz, S.qt, S.n_atoms, S.geom, S.d, 1, key + S.atom_off, S.leaf_off, rank + S.atom_off,
+                  count + S.leaf_off, packed + S.atom_off, nullptr, blockIdx.x - first[s], first[s + 1] - first[s]);
+}
+
+template <int PT>
+__global__ void __launch_bounds__(64) kp_p2m(const PackedSys *__restrict__ sys, const int *__restrict__ first,
+                                             int nsys, const Atom4<float> *__restrict__ sorted,
+                                             const int *__restrict__ start, int p, int K, int KS, int chunk,
+                                             float *__restrict__ Mc, double *__restrict__ qds) {
+  const int s = packed_system(first, nsys, blockIdx.x);
+  const PackedSys &S = sys[s];
+  p2m_body<float, PT>(sorted, start + S.leaf_off, p, K, KS, chunk, Mc + (S.box_off + level_offset(S.d)) * KS,
+                      qds + (int64_t)S.leaf_off * 5, S.geom, S.d, blockIdx.x - first[s]);
+}
+
+// M2M (UP, parent level d - step) or L2L (parent level step - 1) of every system
+template <bool UP, int NP>
+__global__ void __launch_bounds__(1024) kp_updown(const PackedSys *__restrict__ sys, const int *__restrict__ first,
+                                                  int nsys, float *__restrict__ X, const float *__restrict__ A, int K,
+                                                  int KS, int step) {
+  const int s = packed_system(first, nsys, blockIdx.x);
+  const PackedSys &S = sys[s];
+  const int pl = UP ? S.d - step : step - 1;
+  updown_body<float, UP, NP>(X + S.box_off * KS, A, K, KS, level_offset(pl), level_offset(pl + 1),
+                             int64_t(1) << (3 * pl), blockIdx.x - first[s]);
+}
+
+__global__ void __launch_bounds__(1024) kp_lattice(const PackedSys *__restrict__ sys, const float *__restrict__ Mc,
+                                                   float *__restrict__ Lc, const double *__restrict__ LamT, int K,
+                                                   int KS, const double *__restrict__ qds) {
+  const PackedSys &S = sys[blockIdx.x];
+  lattice_body<float>(Mc + S.box_off * KS, Lc + S.box_off * KS, LamT, K, qds + (int64_t)S.leaf_off * 5, S.nleaf,
+                      S.geom);
+}
+
+template <int PT>
+__global__ void __launch_bounds__(64) kp_p2p(const PackedSys *__restrict__ sys, const int *__restrict__ first,
+                                             int nsys, const Atom4<float> *__restrict__ sorted,
+                                             const int *__restrict__ start, const int *__restrict__ perm,
+                                             const float *__restrict__ Lc, int KS, float *__restrict__ phi_sorted,
+                                             double *__restrict__ epart) {
+  const int s = packed_system(first, nsys, blockIdx.x);
+  const PackedSys &S = sys[s];
+  p2p_body<float, PT, true, false>(sorted, nullptr, start + S.leaf_off, perm, (int)S.atom_off,
+                                   Lc + (S.box_off + level_offset(S.d)) * KS, S.geom, S.p2p, phi_sorted, S.F,
+                                   S.pot, epart + S.leaf_off, blockIdx.x - first[s]);
+}
+
+template <int PT>
+__global__ void __launch_bounds__(256) kp_site(const PackedSys *__restrict__ sys, const int *__restrict__ first,
+                                               int nsys, const int *__restrict__ slot_of,
+                                               const double *__restrict__ LamT) {
+  const int s = packed_system(first, nsys, blockIdx.x);
+  const PackedSys &S = sys[s];
+  site_body<float, PT, false>(S.site, S.xyz, slot_of + S.atom_off, S.geom, LamT, S.io, blockIdx.x - first[s]);
+}
+
+__global__ void __launch_bounds__(1024) kp_finalize(const PackedSys *__restrict__ sys,
+                                                    const double *__restrict__ epart) {
+  const PackedSys &S = sys[blockIdx.x];
+  finalize_body(epart + S.leaf_off, S.nleaf, S.io.dE_site, S.n_sites, S.ke, S.E, S.E_qi);
 }
 
 // ---------------------------------------------------------------------------
@@ -1554,11 +1748,11 @@ void launch_tree(const T *xyz, const T *qt, int64_t n, const Geom *g, int d, int
   // slot_of holds the in-leaf arrival ranks until k_leafsort writes the slots;
   // count is zero on entry (cleared at creation and by every k_scan)
   hipLaunchKernelGGL(k_bin<T>, dim3(grid_for(n, 256)), dim3(256), 0, st, xyz, qt, n, g, d, periodic, b.key, b.slot_of,
-                     b.count, b.packed);
+                     b.count, b.packed, b.packed_lo);
   hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, st, b.count, b.start, nleaf);
   hipLaunchKernelGGL(k_scatter, dim3(grid_for(n, 256)), dim3(256), 0, st, b.key, b.slot_of, b.start, b.tmp, n);
   hipLaunchKernelGGL(k_leafsort<T>, dim3((nleaf + 3) / 4), dim3(256), 0, st, b.tmp, b.start, nleaf, b.packed, b.perm,
-                     b.slot_of, b.sorted);
+                     b.slot_of, b.sorted, b.packed_lo, b.sorted_lo);
 }
 
 template <class T>
@@ -1744,8 +1938,9 @@ int p2p_blocks(int d) {
 }
 
 template <class T>
-void launch_p2p(const Atom4<T> *sorted, const int *start, const int *perm, const T *Lleaf, int KS, const Geom *g, int d,
-                int periodic, int p, double ke, T *phi_sorted, T *F, T *pot_user, double *epart, hipStream_t st) {
+void launch_p2p(const Atom4<T> *sorted, const Atom4<T> *sorted_lo, const int *start, const int *perm, const T *Lleaf,
+                int KS, const Geom *g, int d, int periodic, int p, double ke, T *phi_sorted, T *F, T *pot_user,
+                double *epart, hipStream_t st) {
   P2PArgs a;
   a.KS = KS;
   a.d = d;
@@ -1757,20 +1952,27 @@ void launch_p2p(const Atom4<T> *sorted, const int *start, const int *perm, const
   // gradient coefficients in LDS when L, Dx, Dy, Dz fit in 16 KB
   a.dloc = (size_t)4 * a.K * sizeof(T) <= 16384 ? 1 : 0;
   const size_t lds = (size_t)(a.dloc ? 4 : 1) * a.K * sizeof(T);
-  // without forces only the potential is formed (near field and local expansion)
+  // without forces only the potential is formed (near field and local expansion);
+  // with coordinate residuals (float32 above order 8) the pair displacements use them
   const dim3 grid(p2p_blocks<T>(d)), block(64);
   if (p == 8 && F)
-    hipLaunchKernelGGL((k_p2p_l2p<T, 8, true>), grid, block, lds, st, sorted, start, perm, Lleaf, g, a, phi_sorted, F,
-                       pot_user, epart);
+    hipLaunchKernelGGL((k_p2p_l2p<T, 8, true, false>), grid, block, lds, st, sorted, sorted_lo, start, perm, Lleaf, g,
+                       a, phi_sorted, F, pot_user, epart);
   else if (p == 8)
-    hipLaunchKernelGGL((k_p2p_l2p<T, 8, false>), grid, block, lds, st, sorted, start, perm, Lleaf, g, a, phi_sorted, F,
-                       pot_user, epart);
+    hipLaunchKernelGGL((k_p2p_l2p<T, 8, false, false>), grid, block, lds, st, sorted, sorted_lo, start, perm, Lleaf, g,
+                       a, phi_sorted, F, pot_user, epart);
+  else if (F && sorted_lo)
+    hipLaunchKernelGGL((k_p2p_l2p<T, 0, true, true>), grid, block, lds, st, sorted, sorted_lo, start, perm, Lleaf, g,
+                       a, phi_sorted, F, pot_user, epart);
+  else if (sorted_lo)
+    hipLaunchKernelGGL((k_p2p_l2p<T, 0, false, true>), grid, block, lds, st, sorted, sorted_lo, start, perm, Lleaf, g,
+                       a, phi_sorted, F, pot_user, epart);
   else if (F)
-    hipLaunchKernelGGL((k_p2p_l2p<T, 0, true>), grid, block, lds, st, sorted, start, perm, Lleaf, g, a, phi_sorted, F,
-                       pot_user, epart);
+    hipLaunchKernelGGL((k_p2p_l2p<T, 0, true, false>), grid, block, lds, st, sorted, sorted_lo, start, perm, Lleaf, g,
+                       a, phi_sorted, F, pot_user, epart);
   else
-    hipLaunchKernelGGL((k_p2p_l2p<T, 0, false>), grid, block, lds, st, sorted, start, perm, Lleaf, g, a, phi_sorted, F,
-                       pot_user, epart);
+    hipLaunchKernelGGL((k_p2p_l2p<T, 0, false, false>), grid, block, lds, st, sorted, sorted_lo, start, perm, Lleaf, g,
+                       a, phi_sorted, F, pot_user, epart);
 }
 
 template <class T>
@@ -1821,6 +2023,73 @@ void launch_finalize(const double *epart, int nb, const double *dE_site, int ns,
 }
 
 
+// One packed evaluation: octree build over the concatenated atoms and leaves
+// (keys carry each system's first leaf, so one counting sort serves all),
+// P2M, M2M by steps from each system's deepest level, M2L of every level of
+// every system in one launch, the lattice per system, L2L by levels, near
+// field, site correction and energy, all on stream st.
+void launch_packed(const PackedPlan &pp, hipStream_t st) {
+  const PackedSys *sys = pp.sys;
+  const int ns = pp.nsys;
+  hipLaunchKernelGGL(kp_bin, dim3(pp.atoms.blocks), dim3(256), 0, st, sys, pp.atoms.first, ns, pp.key, pp.rank,
+                     pp.count, pp.packed);
+  hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, st, pp.count, pp.start, pp.nleaf);
+  hipLaunchKernelGGL(k_scatter, dim3(grid_for(pp.n_atoms, 256)), dim3(256), 0, st, pp.key, pp.rank, pp.start, pp.tmp,
+                     pp.n_atoms);
+  hipLaunchKernelGGL(k_leafsort<float>, dim3((pp.nleaf + 3) / 4), dim3(256), 0, st, pp.tmp, pp.start, pp.nleaf,
+                     pp.packed, pp.perm, pp.slot_of, pp.sorted, nullptr, nullptr);
+  const size_t p2m_lds = (size_t)pp.chunk * pp.K * sizeof(float);
+  if (pp.p == 8)
+    hipLaunchKernelGGL((kp_p2m<8>), dim3(pp.leaves.blocks), dim3(64), p2m_lds, st, sys, pp.leaves.first, ns,
+                       pp.sorted, pp.start, pp.p, pp.K, pp.KS, pp.chunk, pp.Mc, pp.qds);
+  else
+    hipLaunchKernelGGL((kp_p2m<0>), dim3(pp.leaves.blocks), dim3(64), p2m_lds, st, sys, pp.leaves.first, ns,
+                       pp.sorted, pp.start, pp.p, pp.K, pp.KS, pp.chunk, pp.Mc, pp.qds);
+  const int np_up = updown_np<float>(pp.KS, true), np_dn = updown_np<float>(pp.KS, false);
+  const int threads = std::min(1024, (8 * pp.KS + 63) / 64 * 64);
+  auto updown = [&](bool up, int step, const PackedStage &stg) {
+    if (stg.blocks == 0) return;
+    const size_t lds = (size_t)(up ? np_up : np_dn) * (up ? 16 : 1) * pp.KS * sizeof(float);
+    float *X = up ? pp.Mc : pp.Lc;
+    const float *A = up ? pp.m2m : pp.l2l;
+#define MAHI_KP_UPDOWN(U, N) \
+  hipLaunchKernelGGL((kp_updown<U, N>), dim3(stg.blocks), dim3(threads), lds, st, sys, stg.first, ns, X, A, pp.K, pp.KS, step)
+    if (up) {
+      if (np_up == 8) MAHI_KP_UPDOWN(true, 8);
+      else if (np_up == 4) MAHI_KP_UPDOWN(true, 4);
+      else if (np_up == 2) MAHI_KP_UPDOWN(true, 2);
+      else MAHI_KP_UPDOWN(true, 1);
+    } else {
+      if (np_dn == 8) MAHI_KP_UPDOWN(false, 8);
+      else if (np_dn == 4) MAHI_KP_UPDOWN(false, 4);
+      else if (np_dn == 2) MAHI_KP_UPDOWN(false, 2);
+      else MAHI_KP_UPDOWN(false, 1);
+    }
+#undef MAHI_KP_UPDOWN
+  };
+  for (int j = 1; j <= pp.dmax; ++j) updown(true, j, pp.up[j - 1]);
+  launch_packed_m2l(pp, st);
+  hipLaunchKernelGGL(kp_lattice, dim3(ns), dim3(1024), 0, st, sys, pp.Mc, pp.Lc, pp.LamT, pp.K, pp.KS, pp.qds);
+  for (int l = 1; l <= pp.dmax; ++l) updown(false, l, pp.down[l - 1]);
+  const size_t p2p_lds = (size_t)4 * pp.K * sizeof(float) <= 16384 ? (size_t)4 * pp.K * sizeof(float)
+                                                                     : (size_t)pp.K * sizeof(float);
+  if (pp.p == 8)
+    hipLaunchKernelGGL((kp_p2p<8>), dim3(pp.leaves.blocks), dim3(64), p2p_lds, st, sys, pp.leaves.first, ns,
+                       pp.sorted, pp.start, pp.perm, pp.Lc, pp.KS, pp.phi_sorted, pp.epart);
+  else
+    hipLaunchKernelGGL((kp_p2p<0>), dim3(pp.leaves.blocks), dim3(64), p2p_lds, st, sys, pp.leaves.first, ns,
+                       pp.sorted, pp.start, pp.perm, pp.Lc, pp.KS, pp.phi_sorted, pp.epart);
+  if (pp.sites.blocks > 0) {
+    if (pp.p == 8)
+      hipLaunchKernelGGL((kp_site<8>), dim3(pp.sites.blocks), dim3(256), pp.site_lds, st, sys, pp.sites.first, ns,
+                         pp.slot_of, pp.LamT);
+    else
+      hipLaunchKernelGGL((kp_site<0>), dim3(pp.sites.blocks), dim3(256), pp.site_lds, st, sys, pp.sites.first, ns,
+                         pp.slot_of, pp.LamT);
+  }
+  hipLaunchKernelGGL(kp_finalize, dim3(ns), dim3(1024), 0, st, sys, pp.epart);
+}
+
 #define MAHI_INST(T)                                                                                                 \
   template void launch_bbox<T>(const T *, int64_t, double *, int, Geom *, hipStream_t);                             \
   template void launch_tree<T>(const T *, const T *, int64_t, const Geom *, int, int, TreeBufs<T>, hipStream_t);     \
@@ -1836,9 +2105,10 @@ void launch_finalize(const double *epart, int nb, const double *dE_site, int ns,
   template void updown_table<T>(int, int, const double *const *, T *);                                               \
   template void launch_updown<T>(T *, const T *, int, int, int, bool, hipStream_t);                                   \
   template size_t updown_lds<T>(int, bool);                                                                           \
+  template int updown_np<T>(int, bool);                                                                               \
   template int p2p_blocks<T>(int);                                                                                   \
-  template void launch_p2p<T>(const Atom4<T> *, const int *, const int *, const T *, int, const Geom *, int, int, int, \
-                              double, T *, T *, T *, double *, hipStream_t);                                         \
+  template void launch_p2p<T>(const Atom4<T> *, const Atom4<T> *, const int *, const int *, const T *, int,          \
+                              const Geom *, int, int, int, double, T *, T *, T *, double *, hipStream_t);            \
   template void launch_charge_scale<T>(const SiteArgs &, const double *, T *, hipStream_t);                          \
   template void launch_site<T>(const SiteArgs &, const T *, const int *, const Geom *, const double *,               \
                                const SiteIO<T> &, hipStream_t);

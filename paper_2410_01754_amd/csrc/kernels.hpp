@@ -71,7 +71,58 @@ struct TreeBufs {
   int *key, *count, *start, *tmp, *perm, *slot_of;
   Atom4<T> *packed;  // leaf-local coordinates and scaled charge, input order
   Atom4<T> *sorted;  // the same, leaf order
+  // float32 at orders above 8: the rounding residuals of the leaf-local
+  // coordinates (x, y, z, 0), input and leaf order; null otherwise
+  Atom4<T> *packed_lo = nullptr, *sorted_lo = nullptr;
 };
+
+// ---- packed batch: many periodic float32 systems of one order, every stage
+// one launch over all of them (a block finds its system from its index).
+// Offsets index the batch's concatenated arrays of atoms, leaves (8^d per
+// system) and boxes (levels 0..d per system, then one all-zero row).
+struct PackedSys {
+  int64_t atom_off, n_atoms, box_off;
+  int leaf_off, nleaf, d, n_sites;
+  double ke;
+  const float *xyz;  // the caller's positions [n_atoms][3] (device memory)
+  const float *qt;   // scaled charges (the system's context)
+  Geom *geom;        // the context's geometry; the lattice writes Q, D, S2 into it
+  float *F;          // the caller's forces [n_atoms][3], or null
+  float *pot;        // the caller's potential output [n_atoms], or null
+  double *E;         // energy (the caller's, else the context's)
+  double *E_qi;      // charge-interpolated energy, or null
+  SiteArgs site;     // the context's site tables (maxa, maxf: the largest of the batch)
+  SiteIO<float> io;  // site pass: the batch's potentials, F, dvdl, the context's dE_site
+  M2LPlan plan;      // M2L items of the system over all its levels
+  P2PArgs p2p;
+};
+
+// Block ranges of the per-system stages: system s owns blocks [first[s], first[s + 1]).
+struct PackedStage {
+  const int *first = nullptr;  // device [nsys + 1]
+  int blocks = 0;
+};
+
+struct PackedPlan {
+  const PackedSys *sys = nullptr;  // device [nsys]
+  int nsys = 0, p = 8, K = 81, KS = 88, dmax = 0, nsplit = 1, nleaf = 0, chunk = 1;
+  int64_t n_atoms = 0, nbox = 0;  // totals (nbox: boxes plus the zero row)
+  size_t site_lds = 0;            // dynamic LDS of the site pass
+  PackedStage atoms, leaves, m2l, sites, up[8], down[8];
+  // batch buffers
+  int *key, *rank, *count, *start, *tmp, *perm, *slot_of;
+  Atom4<float> *packed, *sorted;
+  float *phi_sorted, *Mc, *Lc, *part;
+  double *qds, *epart;
+  // tables shared by the systems (one order: identical tables)
+  const float *m2l_tab, *m2m, *l2l;
+  const int4 *lists;
+  const double *LamT;
+};
+
+// One packed evaluation on stream st (every launch on that stream).
+void launch_packed(const PackedPlan &pp, hipStream_t st);
+void launch_packed_m2l(const PackedPlan &pp, hipStream_t st);
 
 hipError_t upload_constants();
 template <class T> void launch_bbox(const T *xyz, int64_t n, double *part, int nblk, Geom *g, hipStream_t st);
@@ -98,14 +149,17 @@ void m2l32_table(const M2LPlan &a, int slot, const double *Tv, float *dst);
 size_t m2l32_table_size(const M2LPlan &a, int nslots);
 template <class T> void updown_table(int K, int KS, const double *const *Tc, T *A);
 template <class T> size_t updown_lds(int KS, bool up);
+template <class T> int updown_np(int KS, bool up);  // parents per block of k_updown
 template <class T> void launch_updown(T *X, const T *A, int p, int KS, int parent_level, bool up, hipStream_t st);
 template <class T> void launch_mfma_probe(const T *A, const T *B, T *C, int rows, int kk, hipStream_t st);
 // the same check for the float32 16x16x4 tile of the M2L kernel for orders up to 8
 void launch_mfma16_probe(const float *A, const float *B, float *C, int rows, int kk, hipStream_t st);
 template <class T> int p2p_blocks(int d);
+// sorted_lo: coordinate residuals (TreeBufs::sorted_lo) for the near field, or null
 template <class T>
-void launch_p2p(const Atom4<T> *sorted, const int *start, const int *perm, const T *Lleaf, int KS, const Geom *g, int d,
-                int periodic, int p, double ke, T *phi_sorted, T *F, T *pot_user, double *epart, hipStream_t st);
+void launch_p2p(const Atom4<T> *sorted, const Atom4<T> *sorted_lo, const int *start, const int *perm, const T *Lleaf,
+                int KS, const Geom *g, int d, int periodic, int p, double ke, T *phi_sorted, T *F, T *pot_user,
+                double *epart, hipStream_t st);
 template <class T> void launch_charge_scale(const SiteArgs &s, const double *lam, T *qt, hipStream_t st);
 template <class T>
 void launch_site(const SiteArgs &s, const T *xyz, const int *slot_of, const Geom *g, const double *LamT,

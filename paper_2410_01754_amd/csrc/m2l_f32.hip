@@ -209,16 +209,16 @@ struct M2L16 {
   static constexpr int AR = (AV + 255) / 256;     // float4 per thread
 };
 
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2)))
-k_m2l16_f32(const float *__restrict__ M, float *__restrict__ Out, const float *__restrict__ Tab,
-            const int4 *__restrict__ lists, M2LPlan a) {
+// Block bid of the launch (a system of a batch passes its own block index).
+__device__ __forceinline__ void m2l16_body(const float *__restrict__ M, float *__restrict__ Out,
+                                           const float *__restrict__ Tab, const int4 *__restrict__ lists,
+                                           const M2LPlan &a, int bid) {
   using G = M2L16<0>;
   constexpr int NS = G::NS, AFL = G::AFL, AR = G::AR;
   __shared__ __attribute__((aligned(16))) float As[2][AFL];
 
   // ---- work item (blocks of one XCD take consecutive items)
   const int nitems = a.nsplit * a.ngroups * a.tile_run;
-  const int bid = blockIdx.x;
   const int item = (bid & 7) * (nitems >> 3) + (bid >> 3);
   const int tile = a.tile0 + item % a.tile_run;
   const int split = item / a.tile_run;
@@ -388,6 +388,27 @@ k_m2l16_f32(const float *__restrict__ M, float *__restrict__ Out, const float *_
   }
 }
 
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2)))
+k_m2l16_f32(const float *__restrict__ M, float *__restrict__ Out, const float *__restrict__ Tab,
+            const int4 *__restrict__ lists, M2LPlan a) {
+  m2l16_body(M, Out, Tab, lists, a, blockIdx.x);
+}
+
+// Packed batch: the M2L items of every level of every system in one launch,
+// writing operator-range partials into the batch's partial array.
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2)))
+kp_m2l16(const PackedSys *__restrict__ sys, const int *__restrict__ first, int nsys, const float *__restrict__ Mc,
+         float *__restrict__ part, const float *__restrict__ Tab, const int4 *__restrict__ lists, int KS) {
+  int lo = 0, hi = nsys;
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (first[mid] <= (int)blockIdx.x) lo = mid;
+    else hi = mid;
+  }
+  const PackedSys &S = sys[lo];
+  m2l16_body(Mc + S.box_off * KS, part + S.box_off * KS, Tab, lists, S.plan, blockIdx.x - first[lo]);
+}
+
 // L[b] = sum over operator ranges s (in order) of the partial locals, for the
 // boxes [b0, b1) of the M2L levels.
 __global__ void k_m2l_reduce(const floatx4 *__restrict__ part, floatx4 *__restrict__ L, int64_t v0, int64_t v1,
@@ -478,6 +499,17 @@ void launch_m2l_f32(const float *M, float *L, float *part, const float *Tab, con
     hipLaunchKernelGGL(k_m2l_reduce, dim3(grid), dim3(256), 0, st, reinterpret_cast<const floatx4 *>(part),
                        reinterpret_cast<floatx4 *>(L), v0, v1, a.nbox * a.KS / 4, a.nsplit);
   }
+}
+
+void launch_packed_m2l(const PackedPlan &pp, hipStream_t st) {
+  if (pp.m2l.blocks == 0) return;
+  hipLaunchKernelGGL(kp_m2l16, dim3(pp.m2l.blocks), dim3(256), 0, st, pp.sys, pp.m2l.first, pp.nsys, pp.Mc, pp.part,
+                     pp.m2l_tab, pp.lists, pp.KS);
+  // every box of the batch: level-0 rows and the zero row hold all-zero partials
+  const int64_t n = pp.nbox * pp.KS / 4;
+  const int grid = (int)std::min<int64_t>((n + 255) / 256, 4096);
+  hipLaunchKernelGGL(k_m2l_reduce, dim3(grid), dim3(256), 0, st, reinterpret_cast<const floatx4 *>(pp.part),
+                     reinterpret_cast<floatx4 *>(pp.Lc), 0, n, n, pp.nsplit);
 }
 
 // Host layout of the float32 M2L operator table: [slot][row group][chunk][r][96]

@@ -362,15 +362,24 @@ def from_system(system, precision: int = 32, order: Optional[int] = None, depth:
 
 
 class Batch:
-    """Evaluate several evaluators together (mahi_batch_*): one fork/join from
-    `stream`.  use_graph=True (graph capture) is refused by this build."""
+    """Evaluate several evaluators together (mahi_batch_*).
 
-    def __init__(self, evaluators: Sequence[Mahi], use_graph: bool = False, stream: Optional[int] = None):
+    packed=False: one fork/join from `stream`, each evaluator's own evaluation.
+    packed=True: every stage one launch over all systems (float32, periodic,
+    one order of at most 8); use_graph=True (packed only) captures those
+    launches into a HIP graph and replays it."""
+
+    GRAPH = 1
+    PACKED = 2
+
+    def __init__(self, evaluators: Sequence[Mahi], use_graph: bool = False, stream: Optional[int] = None,
+                 packed: bool = False):
         self._lib = lib()
         self.evaluators = list(evaluators)
         arr = (ctypes.c_void_p * len(self.evaluators))(*[m._h.value for m in self.evaluators])
         h = ctypes.c_void_p()
-        st = self._lib.mahi_batch_create(ctypes.byref(h), arr, len(self.evaluators), 1 if use_graph else 0,
+        flags = (self.GRAPH if use_graph else 0) | (self.PACKED if packed else 0)
+        st = self._lib.mahi_batch_create(ctypes.byref(h), arr, len(self.evaluators), flags,
                                          ctypes.c_void_p(stream or 0))
         if st != 0:
             raise MahiError(st, self._lib.mahi_batch_last_error(None).decode())

@@ -1,8 +1,11 @@
 """Batched evaluation of many small systems and the autotuner (run on an MI355X).
 
-* A batch (eager fork/join; the captured-graph mode is disabled and its case
+* A batch (eager fork/join; its captured-graph mode is refused and its case
   skipped) gives the same bits as evaluating each system alone, repeatedly,
   after a change of lambda-tilde and with new output buffers.
+* A packed batch (every stage one launch over all systems) agrees with the
+  single evaluations up to float32 rounding; its HIP-graph replays equal its
+  eager calls bit for bit.
 * Systems evaluated with the autotuned order and depth meet the accuracy
   target against the oracle's Ewald sums.
 """
@@ -95,6 +98,108 @@ def test_batch_matches_single_evaluations(use_graph):
         m.close()
 
 
+def _fresh(bufs):
+    for b in bufs:
+        b["E"].zero_()
+        b["F"].zero_()
+        b["dv"].zero_()
+
+
+def _close(bufs, refs, tol):
+    for b, r in zip(bufs, refs):
+        e = abs(b["E"].item() - r["energy"]) / abs(r["energy"])
+        f = rel(b["F"].cpu().numpy(), r["forces"])
+        v = rel(b["dv"].cpu().numpy(), r["dvdl"])
+        assert e <= tol and f <= tol and v <= tol, (e, f, v)
+
+
+def test_packed_batch_matches_single_evaluations():
+    """Packed batch (every stage one launch over all systems, systems of depth
+    2..4): the same arithmetic as evaluating each system alone except the
+    summation order of the M2L operator ranges (float32 rounding), and the
+    oracle's accuracy bound; repeated calls are bit-identical."""
+    import torch
+    import paper_2410_01754_amd as pkg
+    systems = make_batch(n_systems=7, n_min=1500, n_max=30000, seed=80)
+    mods = _build(systems)
+    refs = [m.eval(s.x) for m, s in zip(mods, systems)]
+    bufs = _buffers(systems, torch.float32)
+    batch = pkg.Batch(mods, packed=True)
+    outs = []
+    for rep in range(2):
+        _fresh(bufs)
+        torch.cuda.synchronize()
+        batch.eval_device(_ptrs(bufs))
+        torch.cuda.synchronize()
+        print(f"[gpu] packed batch call {rep}", flush=True)
+        _close(bufs, refs, 1e-5)
+        outs.append([(b["E"].item(), b["F"].cpu().numpy(), b["dv"].cpu().numpy()) for b in bufs])
+    for a, b in zip(outs[0], outs[1]):
+        assert a[0] == b[0] and np.array_equal(a[1], b[1]) and np.array_equal(a[2], b[2])
+    # new weights of one system are read at the next call
+    lam = systems[1].lam_flat().copy()
+    lam[0::2], lam[1::2] = lam[1::2].copy(), lam[0::2].copy()
+    mods[1].set_lambda(lam)
+    refs[1] = mods[1].eval(systems[1].x)
+    batch.eval_device(_ptrs(bufs))
+    torch.cuda.synchronize()
+    _close(bufs, refs, 1e-5)
+    s = systems[0]
+    E, F, dv, _ = hi.hi_periodic(s.x, s.q, s.sites, s.box)
+    assert rel(bufs[0]["F"].cpu().numpy(), F) <= 2e-4 and rel(bufs[0]["dv"].cpu().numpy(), dv) <= 2e-4
+    batch.close()
+    for m in mods:
+        m.close()
+
+
+def test_packed_batch_graph_replays():
+    """The packed launches captured in a HIP graph: every replay equals the eager
+    packed call bit for bit, with eager work and synchronisations between
+    replays, after new weights, and after new output buffers (a new capture)."""
+    import torch
+    import paper_2410_01754_amd as pkg
+    systems = make_batch(n_systems=5, n_min=1500, n_max=12000, seed=81)
+    mods = _build(systems)
+    bufs = _buffers(systems, torch.float32)
+    eager = pkg.Batch(mods, packed=True)
+    eager.eval_device(_ptrs(bufs))
+    torch.cuda.synchronize()
+    ref = [(b["E"].item(), b["F"].cpu().numpy(), b["dv"].cpu().numpy()) for b in bufs]
+    graph = pkg.Batch(mods, packed=True, use_graph=True)
+
+    def same(bs, rs):
+        for b, r in zip(bs, rs):
+            assert b["E"].item() == r[0]
+            assert np.array_equal(b["F"].cpu().numpy(), r[1]) and np.array_equal(b["dv"].cpu().numpy(), r[2])
+
+    for rep in range(3):
+        _fresh(bufs)
+        torch.cuda.synchronize()
+        graph.eval_device(_ptrs(bufs))
+        torch.cuda.synchronize()
+        print(f"[gpu] packed graph replay {rep}", flush=True)
+        same(bufs, ref)
+        _ = (bufs[0]["F"] * 2.0).sum().item()
+    lam = systems[2].lam_flat().copy()
+    lam[0::2], lam[1::2] = lam[1::2].copy(), lam[0::2].copy()
+    mods[2].set_lambda(lam)
+    eager.eval_device(_ptrs(bufs))
+    torch.cuda.synchronize()
+    ref = [(b["E"].item(), b["F"].cpu().numpy(), b["dv"].cpu().numpy()) for b in bufs]
+    _fresh(bufs)
+    graph.eval_device(_ptrs(bufs))
+    torch.cuda.synchronize()
+    same(bufs, ref)
+    bufs2 = _buffers(systems, torch.float32)
+    graph.eval_device(_ptrs(bufs2))
+    torch.cuda.synchronize()
+    same(bufs2, ref)
+    graph.close()
+    eager.close()
+    for m in mods:
+        m.close()
+
+
 def test_autotuned_systems_meet_target():
     systems = make_batch(n_systems=3, n_min=2000, n_max=6000, seed=78)
     mods = _build(systems, precision=32, target=2e-4)
@@ -108,10 +213,17 @@ def test_autotuned_systems_meet_target():
 
 
 def test_batch_graph_mode_is_refused():
+    """Graph capture is only offered for packed batches; a packed batch refuses
+    float64 contexts."""
     import paper_2410_01754_amd as pkg
     systems = make_batch(n_systems=1, n_min=1500, n_max=2000, seed=79)
     mods = _build(systems)
     with pytest.raises(pkg.MahiError) as e:
         pkg.Batch(mods, use_graph=True)
     assert e.value.status == -6
+    m64 = _build(systems, precision=64)
+    with pytest.raises(pkg.MahiError) as e:
+        pkg.Batch(m64, packed=True)
+    assert e.value.status == -6
     mods[0].close()
+    m64[0].close()

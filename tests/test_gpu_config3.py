@@ -9,8 +9,9 @@ MI355X).
   and 4,000 sampled atoms), in both autograd modes (derivatives recomputed in
   the backward pass, or kept from the forward pass).
 * Central differences of the float64 GPU energy at 200 seeded (atom, axis)
-  coordinates (h = 1e-4 nm), at every weight (h = 1e-4) and at 60 sampled form
-  charges (h = 1e-4 e), against the derivatives the same path returns.
+  coordinates (h = 1e-4 nm, with an h/2 extrapolation), at every weight
+  (h = 1e-4) and at 60 sampled form charges (h = 1e-4 e), against the
+  derivatives the same path returns.
 Relative RMS ||a - b|| / ||b|| as in the parity tests.
 """
 import os
@@ -115,19 +116,31 @@ def test_central_differences_float64():
     x = s.x.astype(np.float64)
     base = m.eval(x, dedq=True)
     energy = lambda xx: m.eval(xx, forces=False, dvdl=False)["energy"]  # noqa: E731
-    # positions: F = -dE/dx
+    # positions: F = -dE/dx.  The central difference at h = 1e-4 nm carries a
+    # truncation error h^2/6 |d3E/dx3|, which for the closest pairs of the
+    # uniformly placed waters (a few hundredths of a nm apart) reaches ~1e-4
+    # of their force; the extrapolation (4 D(h/2) - D(h)) / 3 removes the h^2
+    # term, so it is held to the tight bound and the plain difference to 1e-4.
     h = 1e-4
-    fd, an = [], []
-    for i, d in _coordinate_samples(s, 4, h, 200, 1754):
+
+    def diff(i, d, step):
         xp, xm = x.copy(), x.copy()
-        xp[i, d] += h
-        xm[i, d] -= h
-        fd.append(-(energy(xp) - energy(xm)) / (2 * h))
+        xp[i, d] += step
+        xm[i, d] -= step
+        return -(energy(xp) - energy(xm)) / (2 * step)
+
+    fd, fr, an = [], [], []
+    for i, d in _coordinate_samples(s, 4, h, 200, 1754):
+        d1, d2 = diff(i, d, h), diff(i, d, h / 2)
+        fd.append(d1)
+        fr.append((4 * d2 - d1) / 3)
         an.append(base["forces"][i, d])
-    fd, an = np.array(fd), np.array(an)
+    fd, fr, an = np.array(fd), np.array(fr), np.array(an)
     fmax = np.abs(base["forces"]).max()
-    print(f"x: rel RMS {rel(fd, an):.3e}, max |diff| / max |F| {np.abs(fd - an).max() / fmax:.3e}")
-    assert rel(fd, an) <= 1e-6 and np.abs(fd - an).max() <= 1e-5 * fmax
+    print(f"x: rel RMS {rel(fd, an):.3e} (h), {rel(fr, an):.3e} (extrapolated); "
+          f"max |diff| / max |F| {np.abs(fr - an).max() / fmax:.3e}")
+    assert rel(fd, an) <= 1e-4
+    assert rel(fr, an) <= 1e-6 and np.abs(fr - an).max() <= 1e-6 * fmax
     # weights: every lambda-tilde (the energy is quadratic in them, so the
     # central difference is exact up to rounding)
     lam = s.lam_flat()
