@@ -68,20 +68,16 @@ def p2p_pairs(system, depth: int) -> int:
     return int((cnt * nb).sum() - system.n_atoms)
 
 
-M2L_SRC = os.path.join(ROOT, "paper_2410_01754_amd", "csrc", "m2l_f32.hip")
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "m2l_traffic.txt")
-
-
-def m2l_traffic():
-    """HBM bytes per M2L launch from the committed FETCH_SIZE / WRITE_SIZE counter
-    runs (scaled by the copy-kernel calibration), or None when the source file
-    of the float32 M2L kernel has changed since they were taken."""
+def measured_traffic(record: str):
+    """HBM bytes per launch of a kernel from the committed FETCH_SIZE / WRITE_SIZE
+    counter runs (profiles/<record>, scaled by the copy-kernel calibration), or
+    None when the kernel's source file has changed since they were taken."""
     try:
-        with open(TRAFFIC_FILE) as f:
+        with open(os.path.join(ROOT, "profiles", record)) as f:
             rec = json.load(f)
-        with open(M2L_SRC, "rb") as f:
+        with open(os.path.join(ROOT, rec["source"]), "rb") as f:
             sha = hashlib.sha256(f.read()).hexdigest()
-    except (OSError, ValueError):
+    except (OSError, ValueError, KeyError):
         return None
     if rec.get("source_sha256") != sha:
         return None
@@ -119,7 +115,7 @@ def batch_leg(steps: int):
     systems = make_batch()
     mods, bufs = [], []
     for s in systems:
-        p, d = pkg.autotune(True, s.box, s.n_atoms, 32, 2e-4)
+        p, d = pkg.autotune(True, s.box, s.n_atoms, 32, 2e-4, pkg.site_extent(s))
         mods.append(pkg.from_system(s, precision=32, order=p, depth=d))
         bufs.append((torch.from_numpy(s.x).cuda(), torch.zeros(1, dtype=torch.float64, device="cuda"),
                      torch.zeros((s.n_atoms, 3), dtype=torch.float32, device="cuda"),
@@ -353,11 +349,12 @@ def main():
                                "(1,004,296 atoms), depth 5, order 8", "n_atoms": s.n_atoms,
                    "sites": len(s.sites), "forms": s.n_forms, "depth": s.depth, "order": s.order},
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": PEAK_FP32_MATRIX_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / PEAK_FP32_MATRIX_TFLOPS, "traffic": m2l_traffic(),
+                     "frac": achieved / PEAK_FP32_MATRIX_TFLOPS, "traffic": measured_traffic("m2l_traffic.txt"),
                      "kernel": "m2l", "flop_per_launch": m2l_flop},
         "roofline_p2p": {"bound": "alu", "achieved": p2p_tflops, "peak": PEAK_FP32_VECTOR_UNPACKED_TFLOPS,
                          "unit": "TFLOP/s", "frac": p2p_tflops / PEAK_FP32_VECTOR_UNPACKED_TFLOPS,
-                         "traffic": None, "kernel": "p2p_l2p", "flop_per_launch": 20.0 * pairs,
+                         "traffic": measured_traffic("p2p_traffic.txt"), "kernel": "p2p_l2p",
+                         "flop_per_launch": 20.0 * pairs,
                          "frac_of_pair_instruction_bound": pairs / P2P_PAIR_BOUND_PER_S / (stages["p2p_l2p"] * 1e-3)},
         "extra": extra,
     }

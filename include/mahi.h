@@ -229,8 +229,10 @@ mahi_status mahi_dlambda(int n_lambda, const double *lambda, const double *dvdl 
  *      systems (octree build over the concatenated atoms, M2L of every level
  *      of every system together, ...), on the origin stream only; the batch
  *      owns the evaluation buffers (the contexts give their tables, charges,
- *      sites and geometry).  Needs float32 periodic contexts of one order of
- *      at most 8 whose sites fit in local memory (else MAHI_EUNSUPPORTED).
+ *      sites and geometry).  Needs float32 periodic contexts of one order
+ *      whose sites fit in local memory (else MAHI_EUNSUPPORTED).  Above order
+ *      8 the near field uses the leading part of the leaf-local coordinates
+ *      only (no rounding residuals: for orders of production accuracy).
  *      Results agree with single evaluations up to the summation order of
  *      the M2L operator ranges;
  *   MAHI_BATCH_PACKED | MAHI_BATCH_GRAPH: the packed launches are captured once
@@ -251,16 +253,23 @@ void mahi_batch_destroy(mahi_batch *b);
 const char *mahi_batch_last_error(const mahi_batch *b);
 
 /* Parameter choice for one system (host only, no device work).  order: the
- * smallest p whose modelled relative RMS error of forces, dE/dlambda-tilde
- * and dE/dq, err(p) = 1.6e-3 * 2^-(p-4) (fitted to the order sweeps of this
- * library's float64 path against Ewald sums, well-separation 1), is at most
- * half of target_rel_err.  depth: the d in 0..7 that minimises a cost model of
- * one evaluation (near-field pairs, the serial near field of one crowded leaf,
- * M2L translations scaled by (p+1)^4, and a per-level latency; constants
- * measured on MI355X) for n_atoms spread evenly in the cube.  precision 32 cannot reach targets below 2e-5 (float32
+ * smallest p whose modelled relative RMS error of forces and dE/dlambda-tilde
+ * is at most target_rel_err:
+ *   err(p) = 1.75e-4 * 0.41^(p-8)  sites of extent <= 1 nm,
+ *   err(p) = 5.0e-4  * 0.40^(p-8)  larger or unknown (site_extent < 0) extent,
+ * envelopes with a margin of order sweeps of this library against Ewald sums
+ * on water boxes of 900..60,000 atoms with clustered and spread sites (a
+ * spread site's intra-site pairs lie in the far field).  The per-site
+ * tangent dE/dlambda-tilde_r - dE/dlambda-tilde_0 (the lambda forces) of
+ * systems with a few sites scatters up to twice these values.  site_extent: the largest
+ * distance between two atoms of one site (nm).  depth: the d in 0..7 that
+ * minimises a cost model of one evaluation (near-field pairs, the serial near
+ * field of one crowded leaf, M2L translations scaled by (p+1)^4, and a
+ * per-level latency; constants measured on MI355X) for n_atoms spread evenly
+ * in the cube.  precision 32 cannot reach targets below 2e-5 (float32
  * rounding), 64 not below 2e-8 (order 20): MAHI_ERANGE.                     */
-mahi_status mahi_autotune(int periodic, double edge, int64_t n_atoms, int precision, double target_rel_err, int *order,
-                          int *depth);
+mahi_status mahi_autotune(int periodic, double edge, int64_t n_atoms, int precision, double target_rel_err,
+                          double site_extent, int *order, int *depth);
 
 /* Release every host and device resource of the context (NULL is allowed). */
 void mahi_destroy(mahi_ctx *ctx);

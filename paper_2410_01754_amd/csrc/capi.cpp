@@ -516,14 +516,14 @@ bool same_args(const mahi_eval_args &a, const mahi_eval_args &c) {
          a.dvdl_qi == c.dvdl_qi;
 }
 
-// Whether a batch can run packed: float32, periodic, one order of at most 8
-// (the 16x16x4 M2L kernel), and sites whose work arrays fit in local memory at
-// the batch's largest site.
+// Whether a batch can run packed: float32, periodic, one order (shared
+// tables), and sites whose work arrays fit in local memory at the batch's
+// largest site.
 bool packed_ok(const std::vector<mahi_ctx *> &c, int &maxa, int &maxf) {
   maxa = 1;
   maxf = 1;
   for (const mahi_ctx *x : c) {
-    if (x->prec != 32 || !x->periodic || x->p != c[0]->p || x->p > 8 || x->d > 7) return false;
+    if (x->prec != 32 || !x->periodic || x->p != c[0]->p || x->d > 7) return false;
     maxa = std::max(maxa, x->maxa);
     maxf = std::max(maxf, x->maxf);
   }
@@ -571,13 +571,15 @@ std::string packed_setup(mahi_batch *b, int maxa, int maxf) {
   pp.nleaf = leaves;
   pp.nbox = boxes + 1;  // + the all-zero row
   // operator ranges: the fluid makespan model of the single-system plan on the batch's tiles
+  const M2LPlan &p0 = c[0]->plan32;
   {
-    const double slots = 2.0 * (c[0]->n_cu > 0 ? c[0]->n_cu : 256), work = (double)tiles * kListLen;
+    const double slots = 2.0 * (c[0]->n_cu > 0 ? c[0]->n_cu : 256);
+    const double steps = (double)kListLen * p0.nkc, work = (double)tiles * p0.ngroups * steps;
     double best = 1e300;
     pp.nsplit = 1;
     for (int sp = 1; sp <= kM2LMaxSplit; ++sp) {
-      const double item = (double)kListLen / sp;
-      const double cost = std::max(work / slots + 0.5 * item, item) + kListLen / 32.0 * sp;
+      const double item = steps / sp;
+      const double cost = std::max(work / slots + 0.5 * item, item) + steps / 32.0 * sp;
       if (cost < best - 1e-9) {
         best = cost;
         pp.nsplit = sp;
@@ -600,7 +602,7 @@ std::string packed_setup(mahi_batch *b, int maxa, int maxf) {
   stages.push_back(&pp.atoms);
   stage(pp.leaves, [&](int i) { return b->sys_host[i].nleaf; });
   stages.push_back(&pp.leaves);
-  stage(pp.m2l, [&](int i) { return c[i]->plan32.ntiles * pp.nsplit; });
+  stage(pp.m2l, [&](int i) { return c[i]->plan32.ntiles * pp.nsplit * p0.ngroups; });
   stages.push_back(&pp.m2l);
   stage(pp.sites, [&](int i) { return c[i]->M; });
   stages.push_back(&pp.sites);
@@ -1286,18 +1288,26 @@ const char *mahi_batch_last_error(const mahi_batch *b) {
   return b->err.c_str();
 }
 
-mahi_status mahi_autotune(int periodic, double edge, int64_t n_atoms, int precision, double target, int *order,
-                          int *depth) {
+mahi_status mahi_autotune(int periodic, double edge, int64_t n_atoms, int precision, double target,
+                          double site_extent, int *order, int *depth) {
   if (!order || !depth) return MAHI_EINVAL;
   if (periodic != 0 && periodic != 1) return MAHI_EINVAL;
   if (!(is_fin(edge) && edge > 0)) return MAHI_EINVAL;
   if (precision != 32 && precision != 64) return MAHI_EINVAL;
-  if (!(is_fin(target) && target > 0)) return MAHI_EINVAL;
+  if (!(is_fin(target) && target > 0) || !is_fin(site_extent)) return MAHI_EINVAL;
   if (n_atoms < 1 || n_atoms > (int64_t)0x7fffffff - 1) return MAHI_ERANGE;
   if (target < (precision == 32 ? 2e-5 : 2e-8)) return MAHI_ERANGE;
+  // error envelope: the largest relative RMS error of forces and
+  // dE/dlambda-tilde over water boxes of 900..60,000 atoms at their tuned
+  // depths, against Ewald sums, with a margin.  Sites within 1 nm (the
+  // clustered sites span ~0.6 nm) keep their intra-site pairs in the near
+  // field; sites spread over the box (or of unknown extent) put them in the
+  // far field, where the correction inherits the truncation error.
+  const bool spread = site_extent < 0.0 || site_extent > 1.0;
+  const double e8 = spread ? 5.0e-4 : 1.75e-4, f = spread ? 0.40 : 0.41;
   int p = 0;
   for (int c = 1; c <= kMaxOrder && !p; ++c)
-    if (1.6e-3 * std::pow(0.5, c - 4) <= 0.5 * target) p = c;
+    if (e8 * std::pow(f, c - 8) <= target) p = c;
   if (!p) return MAHI_ERANGE;
   // seconds per unit, from the 1,004,296-atom depth-5 order-8 stage times
   const bool f32 = precision == 32;

@@ -36,9 +36,9 @@ typedef float floatx16 __attribute__((ext_vector_type(16)));
 // ---------------------------------------------------------------------------
 
 template <int NS>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2)))
-k_m2l_f32(const float *__restrict__ M, float *__restrict__ Out, const float *__restrict__ Tab,
-          const int4 *__restrict__ lists, M2LPlan a) {
+__device__ __forceinline__ void m2l32_body(const float *__restrict__ M, float *__restrict__ Out,
+                                           const float *__restrict__ Tab, const int4 *__restrict__ lists,
+                                           const M2LPlan &a, int bid) {
   constexpr int RG = kM2LRowGroup;  // rows per group (3 tiles of 32)
   constexpr int KC = 2 * NS;        // operator rows (k values) per chunk
   constexpr int NQ = (NS + 3) / 4;  // float4 loads per lane per chunk
@@ -48,7 +48,6 @@ k_m2l_f32(const float *__restrict__ M, float *__restrict__ Out, const float *__r
 
   // ---- work item (blocks of one XCD take consecutive items)
   const int nitems = a.nsplit * a.ngroups * a.tile_run;
-  const int bid = blockIdx.x;
   const int item = (bid & 7) * (nitems >> 3) + (bid >> 3);
   const int tile = a.tile0 + item % a.tile_run;
   const int rest = item / a.tile_run;
@@ -178,6 +177,13 @@ k_m2l_f32(const float *__restrict__ M, float *__restrict__ Out, const float *__r
     }
 }
 
+template <int NS>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2)))
+k_m2l_f32(const float *__restrict__ M, float *__restrict__ Out, const float *__restrict__ Tab,
+          const int4 *__restrict__ lists, M2LPlan a) {
+  m2l32_body<NS>(M, Out, Tab, lists, a, blockIdx.x);
+}
+
 // ---------------------------------------------------------------------------
 // M2L in float32 for orders up to 8 ((p+1)^2 <= 81) on 16x16x4 matrix-core
 // tiles.  The same work items, operator ranges, XCD mapping and LDS operator
@@ -209,25 +215,22 @@ struct M2L16 {
   static constexpr int AR = (AV + 255) / 256;     // float4 per thread
 };
 
-// Block bid of the launch (a system of a batch passes its own block index).
-__device__ __forceinline__ void m2l16_body(const float *__restrict__ M, float *__restrict__ Out,
-                                           const float *__restrict__ Tab, const int4 *__restrict__ lists,
-                                           const M2LPlan &a, int bid) {
+// One piece of work: operators o0..o1-1 of the interaction list of one tile
+// (128 targets of one parity class of one level); the partial locals go to
+// slot `slot` of the output (Out + slot * nbox boxes).
+__device__ __forceinline__ void m2l16_piece(const float *__restrict__ M, float *__restrict__ Out,
+                                            const float *__restrict__ Tab, const int4 *__restrict__ lists,
+                                            const M2LPlan &a, int tile, int o0, int o1, int slot) {
   using G = M2L16<0>;
   constexpr int NS = G::NS, AFL = G::AFL, AR = G::AR;
   __shared__ __attribute__((aligned(16))) float As[2][AFL];
 
-  // ---- work item (blocks of one XCD take consecutive items)
-  const int nitems = a.nsplit * a.ngroups * a.tile_run;
-  const int item = (bid & 7) * (nitems >> 3) + (bid >> 3);
-  const int tile = a.tile0 + item % a.tile_run;
-  const int split = item / a.tile_run;
   int l = a.lmin;
   while (l < a.d && tile >= a.tiles_start[l + 1]) ++l;
   const int tl = tile - a.tiles_start[l];
   const int cls = tl & 7, chunk = tl >> 3;
-  const int o0 = split * kListLen / a.nsplit, o1 = (split + 1) * kListLen / a.nsplit;
   const int nit = o1 - o0;
+  const int split = slot;
 
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int q = lane >> 4, c = lane & 15;
@@ -388,6 +391,18 @@ __device__ __forceinline__ void m2l16_body(const float *__restrict__ M, float *_
   }
 }
 
+// Block bid of the launch (a system of a batch passes its own block index):
+// item = (tile, operator range), blocks of one XCD take consecutive items.
+__device__ __forceinline__ void m2l16_body(const float *__restrict__ M, float *__restrict__ Out,
+                                           const float *__restrict__ Tab, const int4 *__restrict__ lists,
+                                           const M2LPlan &a, int bid) {
+  const int nitems = a.nsplit * a.ngroups * a.tile_run;
+  const int item = (bid & 7) * (nitems >> 3) + (bid >> 3);
+  const int tile = a.tile0 + item % a.tile_run;
+  const int split = item / a.tile_run;
+  m2l16_piece(M, Out, Tab, lists, a, tile, split * kListLen / a.nsplit, (split + 1) * kListLen / a.nsplit, split);
+}
+
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2)))
 k_m2l16_f32(const float *__restrict__ M, float *__restrict__ Out, const float *__restrict__ Tab,
             const int4 *__restrict__ lists, M2LPlan a) {
@@ -407,6 +422,20 @@ kp_m2l16(const PackedSys *__restrict__ sys, const int *__restrict__ first, int n
   }
   const PackedSys &S = sys[lo];
   m2l16_body(Mc + S.box_off * KS, part + S.box_off * KS, Tab, lists, S.plan, blockIdx.x - first[lo]);
+}
+
+// the same for orders above 8 (32x32x2 tiles, row groups of 96)
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2)))
+kp_m2l32(const PackedSys *__restrict__ sys, const int *__restrict__ first, int nsys, const float *__restrict__ Mc,
+         float *__restrict__ part, const float *__restrict__ Tab, const int4 *__restrict__ lists, int KS) {
+  int lo = 0, hi = nsys;
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (first[mid] <= (int)blockIdx.x) lo = mid;
+    else hi = mid;
+  }
+  const PackedSys &S = sys[lo];
+  m2l32_body<40>(Mc + S.box_off * KS, part + S.box_off * KS, Tab, lists, S.plan, blockIdx.x - first[lo]);
 }
 
 // L[b] = sum over operator ranges s (in order) of the partial locals, for the
@@ -503,8 +532,12 @@ void launch_m2l_f32(const float *M, float *L, float *part, const float *Tab, con
 
 void launch_packed_m2l(const PackedPlan &pp, hipStream_t st) {
   if (pp.m2l.blocks == 0) return;
-  hipLaunchKernelGGL(kp_m2l16, dim3(pp.m2l.blocks), dim3(256), 0, st, pp.sys, pp.m2l.first, pp.nsys, pp.Mc, pp.part,
-                     pp.m2l_tab, pp.lists, pp.KS);
+  if (pp.K <= 81)
+    hipLaunchKernelGGL(kp_m2l16, dim3(pp.m2l.blocks), dim3(256), 0, st, pp.sys, pp.m2l.first, pp.nsys, pp.Mc, pp.part,
+                       pp.m2l_tab, pp.lists, pp.KS);
+  else
+    hipLaunchKernelGGL(kp_m2l32, dim3(pp.m2l.blocks), dim3(256), 0, st, pp.sys, pp.m2l.first, pp.nsys, pp.Mc, pp.part,
+                       pp.m2l_tab, pp.lists, pp.KS);
   // every box of the batch: level-0 rows and the zero row hold all-zero partials
   const int64_t n = pp.nbox * pp.KS / 4;
   const int grid = (int)std::min<int64_t>((n + 255) / 256, 4096);

@@ -127,7 +127,8 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.mahi_batch_last_error.argtypes = [vp]
     lib.mahi_batch_last_error.restype = ctypes.c_char_p
     ip = ctypes.POINTER(ctypes.c_int)
-    lib.mahi_autotune.argtypes = [ctypes.c_int, ctypes.c_double, ctypes.c_int64, ctypes.c_int, ctypes.c_double, ip, ip]
+    lib.mahi_autotune.argtypes = [ctypes.c_int, ctypes.c_double, ctypes.c_int64, ctypes.c_int, ctypes.c_double,
+                                  ctypes.c_double, ip, ip]
     lib.mahi_autotune.restype = ctypes.c_int
     return lib
 
@@ -164,12 +165,27 @@ def _ptr(a: np.ndarray, t):
     return a.ctypes.data_as(ctypes.POINTER(t))
 
 
-def autotune(periodic: bool, edge: float, n_atoms: int, precision: int, target_rel_err: float):
-    """(order, depth) from the library's error and cost models (mahi_autotune)."""
+def autotune(periodic: bool, edge: float, n_atoms: int, precision: int, target_rel_err: float,
+             site_extent: float = -1.0):
+    """(order, depth) from the library's error and cost models (mahi_autotune);
+    site_extent: largest distance between two atoms of one site in nm (< 0: unknown)."""
     o, d = ctypes.c_int(), ctypes.c_int()
     _check(lib().mahi_autotune(1 if periodic else 0, float(edge), int(n_atoms), int(precision), float(target_rel_err),
-                               ctypes.byref(o), ctypes.byref(d)))
+                               float(site_extent), ctypes.byref(o), ctypes.byref(d)))
     return o.value, d.value
+
+
+def site_extent(system) -> float:
+    """Largest distance between two atoms of one site of a synth-style system (nm),
+    with periodic images taken into account; 0 without sites."""
+    ext = 0.0
+    for st in system.sites:
+        x = np.asarray(system.x[st.atoms], dtype=np.float64)
+        d = x[:, None, :] - x[None, :, :]
+        if system.periodic:
+            d -= system.box * np.round(d / system.box)
+        ext = max(ext, float(np.sqrt((d ** 2).sum(-1)).max()))
+    return ext
 
 
 def lambda_tilde(lambdas) -> np.ndarray:
@@ -366,7 +382,7 @@ class Batch:
 
     packed=False: one fork/join from `stream`, each evaluator's own evaluation.
     packed=True: every stage one launch over all systems (float32, periodic,
-    one order of at most 8); use_graph=True (packed only) captures those
+    one order); use_graph=True (packed only) captures those
     launches into a HIP graph and replays it."""
 
     GRAPH = 1

@@ -135,11 +135,22 @@ def test_null_context_is_rejected():
 # ------------------------------------------------------------------ autotuner and batch (host checks)
 
 def test_autotune_reproduces_the_tuned_configurations():
-    # the paper-scale system and the 100k-atom cube at the 2e-4 target of order 8
-    assert pkg.autotune(True, 21.5, 1004296, 32, 2e-4) == (8, 5)
-    assert pkg.autotune(True, 10.0, 100717, 32, 2e-4) == (8, 4)
-    # the 1e-6 target needs order 16 (the float64 parity case)
-    assert pkg.autotune(True, 10.0, 100717, 64, 1e-6)[0] == 16
+    # the paper-scale system and the 100k-atom cube (clustered sites, ~0.6 nm)
+    # at the 2e-4 target of order 8
+    assert pkg.autotune(True, 21.5, 1004296, 32, 2e-4, 0.6) == (8, 5)
+    assert pkg.autotune(True, 10.0, 100717, 32, 2e-4, 0.6) == (8, 4)
+    # spread sites (or an unknown extent) put intra-site pairs in the far field: one order more
+    assert pkg.autotune(True, 10.0, 100717, 32, 2e-4, 5.0)[0] == 9
+    assert pkg.autotune(True, 10.0, 100717, 32, 2e-4)[0] == 9
+    # the 1e-6 target needs order 14..16 (the float64 parity case runs order 16)
+    assert 14 <= pkg.autotune(True, 10.0, 100717, 64, 1e-6, 0.6)[0] <= 16
+    assert 14 <= pkg.autotune(True, 10.0, 100717, 64, 1e-6)[0] <= 16
+
+
+def test_site_extent_of_the_configurations():
+    from synth import make_config
+    assert 0.3 < pkg.site_extent(make_config(0)) < 2.2 * 3 ** 0.5
+    assert pkg.site_extent(make_config(1)) <= 0.6
 
 
 def test_autotune_order_is_monotone_and_depth_grows_with_size():

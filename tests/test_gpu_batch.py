@@ -27,7 +27,7 @@ def _build(systems, precision=32, target=2e-4):
     import paper_2410_01754_amd as pkg
     mods = []
     for s in systems:
-        p, d = pkg.autotune(True, s.box, s.n_atoms, precision, target)
+        p, d = pkg.autotune(True, s.box, s.n_atoms, precision, target, pkg.site_extent(s))
         print(f"[gpu] {s.name} N={s.n_atoms} p={p} d={d} prec={precision}", flush=True)
         mods.append(pkg.from_system(s, precision=precision, order=p, depth=d))
     return mods
@@ -152,6 +152,29 @@ def test_packed_batch_matches_single_evaluations():
         m.close()
 
 
+def test_packed_batch_high_order():
+    """Spread sites get order 9 from the autotuner: the packed batch then runs the
+    32x32x2 M2L kernel; it agrees with single evaluations up to rounding."""
+    import torch
+    import paper_2410_01754_amd as pkg
+    from synth import make_system
+    rng = np.random.default_rng(84)
+    systems = [make_system(int(n / 3), (n / 3 / 33.4) ** (1 / 3), True, [8] * 5, [2] * 5, total_step=None,
+                           clustered=False, seed=int(rng.integers(1 << 30)), name=f"hi{k}")
+               for k, n in enumerate((2500, 9000, 20000))]
+    mods = _build(systems)
+    assert all(m.info()["order"] == 9 for m in mods)
+    refs = [m.eval(s.x) for m, s in zip(mods, systems)]
+    bufs = _buffers(systems, torch.float32)
+    batch = pkg.Batch(mods, packed=True)
+    batch.eval_device(_ptrs(bufs))
+    torch.cuda.synchronize()
+    _close(bufs, refs, 1e-5)
+    batch.close()
+    for m in mods:
+        m.close()
+
+
 def test_packed_batch_graph_replays():
     """The packed launches captured in a HIP graph: every replay equals the eager
     packed call bit for bit, with eager work and synchronisations between
@@ -200,15 +223,39 @@ def test_packed_batch_graph_replays():
         m.close()
 
 
-def test_autotuned_systems_meet_target():
-    systems = make_batch(n_systems=3, n_min=2000, n_max=6000, seed=78)
+def _tangent(dv, s):
+    out, o = [], 0
+    for st in s.sites:
+        nf = st.charges.shape[0]
+        out.extend(dv[o + r] - dv[o] for r in range(1, nf))
+        o += nf
+    return np.array(out)
+
+
+@pytest.mark.parametrize("clustered", [True, False])
+def test_autotuned_systems_meet_target(clustered):
+    """Systems of 3k..60k atoms with clustered or spread two-form sites, each with
+    the autotuned order and depth for 2e-4: energy, forces and dE/dlambda-tilde
+    within the target against the oracle; the tangent (the lambda forces, an
+    RMS over only 4..16 sites here) within twice the target."""
+    from synth import make_system
+    rng = np.random.default_rng(82 if clustered else 83)
+    systems = []
+    for k, n_tot in enumerate((3000, 14000, 60000)):
+        n_s = int(rng.integers(4, 16))
+        n_w = (n_tot - 8 * n_s) // 3
+        edge = (n_w / 33.4) ** (1 / 3)
+        systems.append(make_system(n_w, edge, True, [8] * n_s, [2] * n_s, total_step=None, clustered=clustered,
+                                   seed=int(rng.integers(1 << 30)), name=f"tuned{k}"))
     mods = _build(systems, precision=32, target=2e-4)
     for m, s in zip(mods, systems):
         g = m.eval(s.x)
         E, F, dv, _ = hi.hi_periodic(s.x, s.q, s.sites, s.box)
-        e = (abs(g["energy"] - E) / abs(E), rel(g["forces"], F), rel(g["dvdl"], dv))
-        print(f"{s.name} N={s.n_atoms}: E {e[0]:.2e} F {e[1]:.2e} dVdl {e[2]:.2e}")
-        assert max(e) <= 2e-4
+        e = (abs(g["energy"] - E) / abs(E), rel(g["forces"], F), rel(g["dvdl"], dv),
+             rel(_tangent(g["dvdl"], s), _tangent(dv, s)))
+        print(f"{s.name} N={s.n_atoms} p={m.info()['order']} d={m.info()['depth']}: E {e[0]:.2e} F {e[1]:.2e} "
+              f"dVdl {e[2]:.2e} tangent {e[3]:.2e}")
+        assert max(e[:3]) <= 2e-4 and e[3] <= 4e-4
         m.close()
 
 
