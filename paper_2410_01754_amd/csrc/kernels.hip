@@ -953,14 +953,15 @@ __global__ void k_mfma_probe(const T *__restrict__ A, const T *__restrict__ B, T
 // Near field + far-field evaluation at the atoms + outputs.
 // One 64-lane block per leaf (blocks of one XCD take one contiguous Morton
 // range, i.e. one spatial octant, so neighbour atoms stay in that XCD's L2).
-// The sources are read straight from the sorted atoms, neighbour leaf by
-// neighbour leaf (leaf-local coordinates; the neighbour's offset, which also
-// carries the periodic image shift, is applied to the targets once per
-// neighbour).  A pass covers up to 64 targets of the leaf: each lane owns M
-// targets (p, p + P, ...) and one of G source groups (every G-th source), with
-// M chosen for the best lane utilisation; the G group partials are summed in
-// group order with cross-lane reads.  Only the leaf itself can hold the
-// target atom, so only that neighbour skips r = 0.  Then one lane per target
+// A pass covers up to 64 targets of the leaf: each lane owns M targets (p,
+// p + P, ...) and one of G source groups (every G-th source), with M chosen
+// for the best lane utilisation; the G group partials are summed in group
+// order with cross-lane reads.  The sources (leaf-local coordinates of their
+// own leaves) are staged through LDS in the target leaf's frame as one flat
+// list over the neighbourhood (p2p_wave_lds); a neighbourhood too large for
+// the flat table is read straight from the sorted atoms, neighbour leaf by
+// neighbour leaf, with the offset applied to the targets (p2p_wave).  Only the
+// leaf itself can hold the target atom, so only its sources skip r = 0.  Then one lane per target
 // evaluates the leaf's local expansion (potential and gradient; the gradient's
 // coefficients are formed once per leaf), adds the r^2 part of the lattice
 // remainder, and writes the potential (sorted order), the force (user order)
@@ -1139,6 +1140,166 @@ __device__ __forceinline__ void p2p_wave(const Atom4<T> *__restrict__ sorted, co
   }
 }
 
+// Staged near field.  The sources of a pass are the leaf itself (self pairs
+// skipped) and then the other 26 neighbours as one flat list: flat source k
+// belongs to neighbour slot seg[k] (a byte table built once per leaf) and sits
+// at sorted index base[seg[k]] + k.  Sources are staged in LDS in the target
+// leaf's frame (the neighbour offset, which also carries the periodic image
+// shift, is added once per source; with residuals the shift is an exact
+// two-sum), kP2PChunk at a time, with the next chunk's loads in flight while
+// the current one is used.  Every lane of the wave runs the same number of
+// steps, ceil(chunk / G): slots past the last source hold a zero charge far
+// away.  Against one pass per neighbour this removes the per-neighbour
+// rounding up of the step count (lane utilisation 0.81 -> 0.92 on ~30-atom
+// leaves), the clamped global addressing of every source and the wait for
+// each source's load.
+constexpr int kP2PChunk = 256;
+constexpr int kP2PSlots = kP2PChunk + 128;
+constexpr int kP2PFlatMax = 2048;  // larger neighbourhoods take the direct path
+
+template <class T>
+struct P2PStage {
+  Atom4<T> o[kP2PChunk / 64], l[kP2PChunk / 64];
+  int r[kP2PChunk / 64];
+};
+
+// Loads of one chunk, branch-free (an index past the end re-reads source 0 and
+// is marked empty), so that all of them are in flight together.
+template <class T, bool SELF, bool LO>
+__device__ __forceinline__ void p2p_stage_load(const Atom4<T> *__restrict__ sorted, const Atom4<T> *__restrict__ sorted_lo,
+                                               const unsigned char *seg, const int *base, const int *rof, int total,
+                                               int c, int lane, P2PStage<T> &st) {
+#pragma unroll
+  for (int i = 0; i < kP2PChunk / 64; ++i) {
+    const int k = c * kP2PChunk + 64 * i + lane;
+    const bool ok = k < total;
+    const int kk = ok ? k : 0;
+    const int sg = SELF ? 26 : (int)seg[kk];
+    const int idx = base[sg] + kk;
+    st.r[i] = ok ? rof[sg] : -1;
+    st.o[i] = sorted[idx];
+    if constexpr (LO) st.l[i] = sorted_lo[idx];
+  }
+}
+
+template <class T, bool LO>
+__device__ __forceinline__ void p2p_stage_store(const P2PStage<T> &st, int lane, Atom4<T> *buf, Atom4<T> *bufl) {
+#pragma unroll
+  for (int i = 0; i < kP2PChunk / 64; ++i) {
+    const int r = st.r[i];
+    Atom4<T> o{T(1e4), T(0), T(0), T(0)}, l{T(0), T(0), T(0), T(0)};
+    if (r >= 0) {
+      const T sx = (T)(r / 9 - 1), sy = (T)((r / 3) % 3 - 1), sz = (T)(r % 3 - 1);
+      const Atom4<T> a = st.o[i];
+      o.x = a.x + sx;
+      o.y = a.y + sy;
+      o.z = a.z + sz;
+      o.q = a.q;
+      if constexpr (LO) {
+        // exact two-sum of the shift plus the stored residual
+        const Atom4<T> b = st.l[i];
+        T bp = o.x - a.x;
+        l.x = ((a.x - (o.x - bp)) + (sx - bp)) + b.x;
+        bp = o.y - a.y;
+        l.y = ((a.y - (o.y - bp)) + (sy - bp)) + b.y;
+        bp = o.z - a.z;
+        l.z = ((a.z - (o.z - bp)) + (sz - bp)) + b.z;
+      }
+    }
+    buf[64 * i + lane] = o;
+    if constexpr (LO) bufl[64 * i + lane] = l;
+  }
+}
+
+template <class T, int M, bool SELF, bool FIELD, bool LO>
+__device__ __forceinline__ void p2p_segment(const Atom4<T> *__restrict__ sorted, const Atom4<T> *__restrict__ sorted_lo,
+                                            const unsigned char *seg, const int *base, const int *rof, int total,
+                                            int lane, int g, int G, Atom4<T> *buf, Atom4<T> *bufl, const T (&qx)[M],
+                                            const T (&qy)[M], const T (&qz)[M], const T (&qxl)[M], const T (&qyl)[M],
+                                            const T (&qzl)[M], T (&phi)[M], T (&ex)[M], T (&ey)[M], T (&ez)[M]) {
+  const int nch = (total + kP2PChunk - 1) / kP2PChunk;
+  P2PStage<T> st;
+  if (nch > 0) p2p_stage_load<T, SELF, LO>(sorted, sorted_lo, seg, base, rof, total, 0, lane, st);
+  for (int c = 0; c < nch; ++c) {
+    __syncthreads();  // the previous chunk's reads are done
+    p2p_stage_store<T, LO>(st, lane, buf, bufl);
+    __syncthreads();
+    if (c + 1 < nch) p2p_stage_load<T, SELF, LO>(sorted, sorted_lo, seg, base, rof, total, c + 1, lane, st);
+    if (g < G) {
+      const int nc = min(kP2PChunk, total - c * kP2PChunk);
+      const int steps = (nc + G - 1) / G;
+      const Atom4<T> zero{T(0), T(0), T(0), T(0)};
+      int i = 0;
+      for (; i + 1 < steps; i += 2) {
+        const int j = g + i * G;
+        const Atom4<T> o0 = buf[j], o1 = buf[j + G];
+        const Atom4<T> l0 = LO ? bufl[j] : zero, l1 = LO ? bufl[j + G] : zero;
+        p2p_pair<T, M, SELF, FIELD, LO>(o0, l0, qx, qy, qz, qxl, qyl, qzl, phi, ex, ey, ez);
+        p2p_pair<T, M, SELF, FIELD, LO>(o1, l1, qx, qy, qz, qxl, qyl, qzl, phi, ex, ey, ez);
+      }
+      if (i < steps) {
+        const int j = g + i * G;
+        const Atom4<T> o0 = buf[j];
+        const Atom4<T> l0 = LO ? bufl[j] : zero;
+        p2p_pair<T, M, SELF, FIELD, LO>(o0, l0, qx, qy, qz, qxl, qyl, qzl, phi, ex, ey, ez);
+      }
+    }
+  }
+}
+
+template <class T, int M, bool FIELD, bool LO>
+__device__ __forceinline__ void p2p_wave_lds(const Atom4<T> *__restrict__ sorted,
+                                             const Atom4<T> *__restrict__ sorted_lo, const unsigned char *seg,
+                                             const int *base, const int *rof, int n_self, int n_other,
+                                             Atom4<T> *buf, Atom4<T> *bufl, int tp, int nt, int lane, P2PPass ps,
+                                             T (&acc)[4]) {
+  const int p = lane % ps.P, g = lane / ps.P;
+  T qx[M], qy[M], qz[M], qxl[M], qyl[M], qzl[M], phi[M], ex[M], ey[M], ez[M];
+#pragma unroll
+  for (int m = 0; m < M; ++m) {
+    const int u = p + m * ps.P;
+    Atom4<T> me = {T(0), T(0), T(0), T(0)}, ml = {T(0), T(0), T(0), T(0)};
+    if (u < nt) {
+      me = sorted[tp + u];
+      if constexpr (LO) ml = sorted_lo[tp + u];
+    }
+    qx[m] = me.x;
+    qy[m] = me.y;
+    qz[m] = me.z;
+    qxl[m] = ml.x;
+    qyl[m] = ml.y;
+    qzl[m] = ml.z;
+    phi[m] = ex[m] = ey[m] = ez[m] = T(0);
+  }
+  // the other 26 neighbours, then the leaf itself (table slot 26, no flat
+  // table): the leaf holds most of the close pairs, whose large terms come
+  // last so that the many small ones are not added to a large partial sum
+  p2p_segment<T, M, false, FIELD, LO>(sorted, sorted_lo, seg, base, rof, n_other, lane, g, ps.G, buf, bufl, qx, qy,
+                                      qz, qxl, qyl, qzl, phi, ex, ey, ez);
+  p2p_segment<T, M, true, FIELD, LO>(sorted, sorted_lo, nullptr, base, rof, n_self, lane, g,
+                                     ps.G, buf, bufl, qx, qy, qz, qxl, qyl, qzl, phi, ex, ey, ez);
+  const int pu = lane % ps.P, mu = lane / ps.P;
+#pragma unroll
+  for (int m = 0; m < M; ++m) {
+    T s0 = T(0), s1 = T(0), s2 = T(0), s3 = T(0);
+    for (int gg = 0; gg < ps.G; ++gg) {
+      const int sl = gg * ps.P + pu;
+      s0 += shfl_t(phi[m], sl);
+      if constexpr (FIELD) {
+        s1 += shfl_t(ex[m], sl);
+        s2 += shfl_t(ey[m], sl);
+        s3 += shfl_t(ez[m], sl);
+      }
+    }
+    if (mu == m) {
+      acc[0] += s0;
+      acc[1] += s1;
+      acc[2] += s2;
+      acc[3] += s3;
+    }
+  }
+}
+
 // Block bid handles one leaf.  perm holds atom indices of the whole batch:
 // perm_off (the system's first atom) turns them into indices of F and pot_user.
 template <class T, int PT, bool FIELD, bool LO>
@@ -1151,6 +1312,10 @@ __device__ __forceinline__ void p2p_body(const Atom4<T> *__restrict__ sorted, co
   extern __shared__ unsigned char smem_raw[];
   T *loc = reinterpret_cast<T *>(smem_raw);  // [KL]: L, then (dloc) Dx, Dy, Dz
   __shared__ int nb_st[27], nb_ct[27];
+  __shared__ int p2p_base[27], p2p_rof[27], p2p_tot;
+  __shared__ unsigned char p2p_seg[kP2PFlatMax];
+  __shared__ Atom4<T> sbuf[kP2PSlots];
+  __shared__ Atom4<T> sbufl[LO ? kP2PSlots : 1];
 
   const int lane = threadIdx.x;
   const int n = 1 << a.d;
@@ -1179,7 +1344,31 @@ __device__ __forceinline__ void p2p_body(const Atom4<T> *__restrict__ sorted, co
     nb_ct[lane] = cnt;
   }
   for (int e = lane; e < a.K; e += 64) loc[e] = Lleaf[(int64_t)leaf * a.KS + e];
+  // permanent far-away zero-charge slots past the chunk (steps run past the last source)
+  for (int e = kP2PChunk + lane; e < kP2PSlots; e += 64) {
+    sbuf[e] = Atom4<T>{T(1e4), T(0), T(0), T(0)};
+    if constexpr (LO) sbufl[e] = Atom4<T>{T(0), T(0), T(0), T(0)};
+  }
   __syncthreads();
+  // flat source tables: slots 0..25 the other neighbours in order, slot 26 the leaf itself
+  {
+    int acc = 0;
+    for (int sg = 0; sg < 26; ++sg) {
+      const int r = sg < 13 ? sg : sg + 1;
+      const int cnt = nb_ct[r];
+      if (lane == 0) {
+        p2p_base[sg] = nb_st[r] - acc;
+        p2p_rof[sg] = r;
+      }
+      for (int k = acc + lane; k < acc + cnt && k < kP2PFlatMax; k += 64) p2p_seg[k] = (unsigned char)sg;
+      acc += cnt;
+    }
+    if (lane == 0) {
+      p2p_base[26] = nb_st[13];
+      p2p_rof[26] = 13;
+      p2p_tot = acc;
+    }
+  }
   if (FIELD && a.dloc) {
     // gradient coefficients Dx, Dy, Dz in the real packing of L (degrees < p)
     const int nd = a.p * a.p;
@@ -1209,9 +1398,22 @@ __device__ __forceinline__ void p2p_body(const Atom4<T> *__restrict__ sorted, co
     int M;
     const P2PPass ps = p2p_pass_shape(nt, M);
     T acc[4] = {T(0), T(0), T(0), T(0)};
-    if (M == 1) p2p_wave<T, 1, FIELD, LO>(sorted, sorted_lo, nb_st, nb_ct, tp, nt, lane, ps, acc);
-    else if (M == 2) p2p_wave<T, 2, FIELD, LO>(sorted, sorted_lo, nb_st, nb_ct, tp, nt, lane, ps, acc);
-    else p2p_wave<T, 3, FIELD, LO>(sorted, sorted_lo, nb_st, nb_ct, tp, nt, lane, ps, acc);
+    if (p2p_tot <= kP2PFlatMax) {
+      if (M == 1)
+        p2p_wave_lds<T, 1, FIELD, LO>(sorted, sorted_lo, p2p_seg, p2p_base, p2p_rof, nt_leaf, p2p_tot, sbuf, sbufl,
+                                      tp, nt, lane, ps, acc);
+      else if (M == 2)
+        p2p_wave_lds<T, 2, FIELD, LO>(sorted, sorted_lo, p2p_seg, p2p_base, p2p_rof, nt_leaf, p2p_tot, sbuf, sbufl,
+                                      tp, nt, lane, ps, acc);
+      else
+        p2p_wave_lds<T, 3, FIELD, LO>(sorted, sorted_lo, p2p_seg, p2p_base, p2p_rof, nt_leaf, p2p_tot, sbuf, sbufl,
+                                      tp, nt, lane, ps, acc);
+    } else {
+      // neighbourhoods beyond the flat table: one pass per neighbour from global memory
+      if (M == 1) p2p_wave<T, 1, FIELD, LO>(sorted, sorted_lo, nb_st, nb_ct, tp, nt, lane, ps, acc);
+      else if (M == 2) p2p_wave<T, 2, FIELD, LO>(sorted, sorted_lo, nb_st, nb_ct, tp, nt, lane, ps, acc);
+      else p2p_wave<T, 3, FIELD, LO>(sorted, sorted_lo, nb_st, nb_ct, tp, nt, lane, ps, acc);
+    }
     if (lane < nt) {
       const int ti = tp + lane;
       const Atom4<T> me = sorted[ti];

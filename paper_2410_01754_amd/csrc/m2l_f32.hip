@@ -14,6 +14,41 @@ namespace mahi {
 
 typedef float floatx16 __attribute__((ext_vector_type(16)));
 
+// Source boxes by subtraction of dilated integers.  With a target's Morton
+// index split into its x, y and z bits (t & mx, t & my, t & mz), the x bits of
+// the index of box (x - dx) mod 2^l are ((t & mx) - dil(dx)) & mx: borrows run
+// through the other axes' bit positions and are masked off, and the l-bit
+// field wraps as the periodic lattice does.  The dilated offsets are the same
+// for the whole wave (scalar work); a lane spends 3 subtractions, 3 masks and
+// an OR per source instead of interleaving its coordinates.
+__device__ __forceinline__ uint32_t dilate3(uint32_t v) {
+  v &= 0x3ffu;
+  v = (v | (v << 16)) & 0x030000FFu;
+  v = (v | (v << 8)) & 0x0300F00Fu;
+  v = (v | (v << 4)) & 0x030C30C3u;
+  v = (v | (v << 2)) & 0x09249249u;
+  return v;
+}
+
+struct AxisMasks {
+  uint32_t x, y, z;
+};
+
+__device__ __forceinline__ AxisMasks axis_masks(int l) {
+  const uint32_t mz = spread3((1u << l) - 1u);
+  return {mz << 2, mz << 1, mz};
+}
+
+// Morton index (level-local) of the box at offset -v from the target whose
+// index t has been split by the masks into tx, ty, tz.
+__device__ __forceinline__ uint32_t dilated_source(const AxisMasks &m, uint32_t tx, uint32_t ty, uint32_t tz,
+                                                   const int4 &v) {
+  const uint32_t vx = (dilate3((uint32_t)v.x) << 2) & m.x;
+  const uint32_t vy = (dilate3((uint32_t)v.y) << 1) & m.y;
+  const uint32_t vz = dilate3((uint32_t)v.z) & m.z;
+  return ((tx - vx) & m.x) | ((ty - vy) & m.y) | ((tz - vz) & m.z);
+}
+
 // ---------------------------------------------------------------------------
 // M2L in float32 on the matrix cores, operator shared through LDS.
 // Work item: (level, parity class, 128 consecutive targets of that class, row
@@ -72,20 +107,18 @@ __device__ __forceinline__ void m2l32_body(const float *__restrict__ M, float *_
   if (valid) unmorton((uint32_t)(8 * P + cls), tx, ty, tz);
   const int64_t off = level_offset(l);
   const int4 *lst = lists + cls * kListLen;
+  const AxisMasks am = axis_masks(l);
+  const uint32_t tm = (uint32_t)(8 * P + cls);
+  const uint32_t tmx = tm & am.x, tmy = tm & am.y, tmz = tm & am.z;
 
   // source row (in boxes) of operator iteration `it`, or the all-zero row
   auto src_row = [&](int it) -> int64_t {
     const int4 v = lst[o0 + it / a.nkc];
-    int sx = tx - v.x, sy = ty - v.y, sz = tz - v.z;
     bool ok = valid;
-    if (a.periodic) {
-      sx = (sx + 4 * nl) & (nl - 1);
-      sy = (sy + 4 * nl) & (nl - 1);
-      sz = (sz + 4 * nl) & (nl - 1);
-    } else {
-      ok = ok && (unsigned)sx < (unsigned)nl && (unsigned)sy < (unsigned)nl && (unsigned)sz < (unsigned)nl;
-    }
-    return ok ? off + (int64_t)morton(sx, sy, sz) : a.zbox;
+    if (!a.periodic)
+      ok = ok && (unsigned)(tx - v.x) < (unsigned)nl && (unsigned)(ty - v.y) < (unsigned)nl &&
+           (unsigned)(tz - v.z) < (unsigned)nl;
+    return ok ? off + (int64_t)dilated_source(am, tmx, tmy, tmz, v) : a.zbox;
   };
   auto load_b = [&](int it, float *b) {
     const int c = it % a.nkc;
@@ -250,20 +283,24 @@ __device__ __forceinline__ void m2l16_piece(const float *__restrict__ M, float *
   }
   const int64_t off = level_offset(l);
   const int4 *lst = lists + cls * kListLen;
+  const AxisMasks am = axis_masks(l);
+  uint32_t tmx[2], tmy[2], tmz[2];
+#pragma unroll
+  for (int hf = 0; hf < 2; ++hf) {
+    const uint32_t tm = (uint32_t)(8 * Ph[hf] + cls);
+    tmx[hf] = tm & am.x;
+    tmy[hf] = tm & am.y;
+    tmz[hf] = tm & am.z;
+  }
 
   // source row of target half hf for operator iteration it, or the all-zero row
   auto src_row = [&](int it, int hf) -> int64_t {
     const int4 v = lst[o0 + it];
-    int sx = tx[hf] - v.x, sy = ty[hf] - v.y, sz = tz[hf] - v.z;
     bool ok = valid[hf];
-    if (a.periodic) {
-      sx = (sx + 4 * nl) & (nl - 1);
-      sy = (sy + 4 * nl) & (nl - 1);
-      sz = (sz + 4 * nl) & (nl - 1);
-    } else {
-      ok = ok && (unsigned)sx < (unsigned)nl && (unsigned)sy < (unsigned)nl && (unsigned)sz < (unsigned)nl;
-    }
-    return ok ? off + (int64_t)morton(sx, sy, sz) : a.zbox;
+    if (!a.periodic)
+      ok = ok && (unsigned)(tx[hf] - v.x) < (unsigned)nl && (unsigned)(ty[hf] - v.y) < (unsigned)nl &&
+           (unsigned)(tz[hf] - v.z) < (unsigned)nl;
+    return ok ? off + (int64_t)dilated_source(am, tmx[hf], tmy[hf], tmz[hf], v) : a.zbox;
   };
   // b[hf][s]: k = 20q + s (s < 20), 80 + q (s = 20)
   auto load_b = [&](int it, float (*b)[NS]) {
