@@ -14,10 +14,11 @@ Reported next to the headline ns/eval:
     of the near field (P2P + L2P, bound by the vector ALU),
   * the site correction alone (mahi_correct) on a given potential,
   * a batch of 96 small systems (3k..60k atoms, autotuned order and depth):
-    per-system latency and eager batched throughput (extra.batch96),
-  * the CPU oracle on a bounded sample (same recipe, smaller cubes), scaled to
-    the full system by the oracle's reciprocal-space work (--cpu-full also
-    times it on the whole workload, which takes minutes).
+    per-system latency and the packed batch's throughput (extra.batch96),
+  * the CPU oracle on bounded samples of the full system (atom subsets for its
+    reciprocal sums, sampled targets for its real-space sums), scaled part by
+    part with its cost model (--cpu-full also times it on the whole workload,
+    which takes minutes).
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-batch] [--cpu-full]
 """
@@ -169,19 +170,6 @@ def batch_leg(steps: int):
             "order_histogram": {str(o): orders.count(o) for o in sorted(set(orders))}}
 
 
-def oracle_kspace_work(n: int, edge: float) -> float:
-    """Phase evaluations e^{ik.x} of the oracle's reciprocal-space sums for n atoms
-    in a cube of this edge: the structure factor over all atoms plus the sum at
-    every atom, 2 n n_k, with the oracle's own splitting parameter and cutoffs."""
-    from oracle import ewald
-    a = ewald.default_alpha(n, edge)
-    _, mmax = ewald.cutoffs(a, edge)
-    m = np.arange(-mmax, mmax + 1)
-    m2 = m[:, None, None] ** 2 + m[None, :, None] ** 2 + m[None, None, :] ** 2
-    nk = int(((m2 <= mmax * mmax).sum() - 1) // 2)
-    return 2.0 * n * nk
-
-
 def oracle_threads() -> int:
     """Threads the oracle runs on: the host's cores, capped by OMP_NUM_THREADS when set."""
     t = os.cpu_count() or 1
@@ -192,47 +180,66 @@ def oracle_threads() -> int:
     return max(1, t)
 
 
-def cpu_baseline(full_n: int, full_edge: float, full_system=None):
-    """The oracle (float64 Ewald HI, every thread of oracle_threads()) timed on
-    smaller cubes of the same recipe, scaled to the full system by its
-    reciprocal-space work (2 N n_k phase evaluations, the term that dominates
-    the oracle's cost: a fit with a real-space term gives it no weight), using
-    the time per unit of work of the largest sample.  With full_system the
-    oracle is also timed on the whole workload (minutes)."""
-    from oracle import hi
-    from synth import make_system
+def cpu_baseline(system, full: bool = False):
+    """The oracle (float64 Ewald HI on every thread of oracle_threads()) on a
+    bounded sample of the full workload, scaled part by part with its cost
+    model.  The oracle's time is the sum of
+      * the reciprocal-space sums: a structure-factor table of n_k entries per
+        thread updated by every atom, then one pass over the table per target
+        (both linear in the atom count at fixed n_k, plus a per-k setup).
+        Timed on 1/64 and 1/16 of the atoms in the full box with the full
+        system's splitting parameter, so that n_k and the table keep their
+        full sizes (and their cache behaviour); extrapolated linearly in N;
+      * the real-space sums: per target a cell-list walk at full density.
+        Timed for 16,384 sampled targets of the full system with the
+        reciprocal sums switched off (no k-vectors), scaled by N / 16,384;
+      * the per-site pair sums of the HI step, timed in full.
+    With full=True the oracle also runs on the whole workload (minutes)."""
+    import ctypes
+    from oracle import ewald, hi
     th = oracle_threads()
-    pts, small = [], None
-    for edge in (6.0, 8.5, 11.0):
-        nw = int(round(33.4 * edge ** 3))
-        ns = max(1, int(round(3 * nw / 1960)))
-        s = make_system(nw, edge, True, [8] * ns, [2] * ns, total_step=1.0, depth=3, seed=7)
-        small = small if pts else s
+    N, L = system.n_atoms, system.box
+    x = np.ascontiguousarray(system.x, dtype=np.float64)
+    qt, _ = hi.scaled_charges(N, system.q, system.sites)
+    alpha = ewald.default_alpha(N, L)
+    rc, mmax = ewald.cutoffs(alpha, L)
+    rng = np.random.default_rng(7)
+    t_start = time.perf_counter()
+    ks = []
+    for frac in (64, 16):
+        idx = np.sort(rng.choice(N, N // frac, replace=False))
         t0 = time.perf_counter()
-        hi.hi_periodic(s.x, s.q, s.sites, s.box, nthreads=th)
-        pts.append((s.n_atoms, edge, time.perf_counter() - t0))
-    w_full = oracle_kspace_work(full_n, full_edge)
-    n_l, e_l, t_l = pts[-1]
-    t_full = t_l * w_full / oracle_kspace_work(n_l, e_l)
-    expo, icpt = np.polyfit(np.log([p[0] for p in pts]), np.log([p[2] for p in pts]), 1)
-    t_pow = float(np.exp(icpt + expo * np.log(full_n)))
-    desc = ", ".join(f"{e:g} nm {n} atoms {t:.2f} s" for n, e, t in pts)
-    s = small
+        ewald.field(x[idx], qt[idx], L, alpha=alpha, nthreads=th)
+        ks.append((int(idx.shape[0]), time.perf_counter() - t0))
+    slope = (ks[1][1] - ks[0][1]) / (ks[1][0] - ks[0][0])
+    t_recip = ks[0][1] + slope * (N - ks[0][0])
+    T = min(16384, N)
+    tg = np.sort(rng.choice(N, T, replace=False)).astype(np.int64)
+    phi, fld = np.zeros(T), np.zeros((T, 3))
+    lib = ewald._load()
     t0 = time.perf_counter()
-    hi.hi_periodic(s.x, s.q, s.sites, s.box, nthreads=1)
-    t1 = time.perf_counter() - t0
-    t1_full = t1 * w_full / oracle_kspace_work(s.n_atoms, s.box)
+    rcode = lib.ew_field(N, ewald._ptr(x), ewald._ptr(qt), L, alpha, rc, 0, T, ewald._ptr(tg, ctypes.c_int64),
+                         ewald._ptr(phi), ewald._ptr(fld), th)
+    t_real_s = time.perf_counter() - t0
+    if rcode != 0:
+        raise RuntimeError("oracle real-space sample failed")
+    t_real = t_real_s * N / T
+    d = np.concatenate([(x[st.atoms][:, None, :] - x[st.atoms][None, :, :]).reshape(-1, 3) for st in system.sites])
+    t0 = time.perf_counter()
+    ewald.pair(d, L, nthreads=th)
+    t_pair = time.perf_counter() - t0
+    t_full = t_recip + t_real + t_pair
     out = {"value": t_full * 1e9, "unit": "ns/eval", "cores": th, "kind": "oracle",
-           "sample": f"full HI evaluation of 6, 8.5 and 11 nm cubes of the same recipe on {th} threads ({desc}); "
-                     f"scaled to {full_n} atoms by the oracle's reciprocal-space work (2 N n_k phase "
-                     f"evaluations: {w_full:.3e} against {oracle_kspace_work(n_l, e_l):.3e} for the 11 nm cube)",
-           "power_law_value": t_pow * 1e9, "power_law_exponent": float(expo),
-           "single_core_value": t1_full * 1e9,
-           "single_core_sample": f"the 6 nm cube on one thread ({s.n_atoms} atoms {t1:.2f} s), same work scaling"}
-    if full_system is not None:
-        s = full_system
+           "sample": (f"the oracle on {th} threads, full system scaled part by part: reciprocal sums timed on "
+                      f"{ks[0][0]} and {ks[1][0]} atoms of the full box with its splitting parameter "
+                      f"({ks[0][1]:.2f} s, {ks[1][1]:.2f} s; n_k at full size, linear in N -> {t_recip:.0f} s), "
+                      f"real-space sums for {T} sampled targets of the full system ({t_real_s:.2f} s -> "
+                      f"{t_real:.0f} s), site pair sums {t_pair:.2f} s; "
+                      f"{time.perf_counter() - t_start:.0f} s of sampling"),
+           "parts_s": {"reciprocal": t_recip, "real": t_real, "site_pairs": t_pair}}
+    if full:
         t0 = time.perf_counter()
-        hi.hi_periodic(s.x, s.q, s.sites, s.box, nthreads=th)
+        hi.hi_periodic(system.x, system.q, system.sites, system.box, nthreads=th)
         out["measured_full_value"] = (time.perf_counter() - t0) * 1e9
     return out
 
@@ -362,7 +369,7 @@ def main():
         extra["batch96"] = batch_leg(max(3, args.steps // 4))
         print(f"[bench] batch {extra['batch96']}", file=sys.stderr, flush=True)
     if not args.no_cpu:
-        line["cpu_baseline"] = cpu_baseline(s.n_atoms, s.box, s if args.cpu_full else None)
+        line["cpu_baseline"] = cpu_baseline(s, args.cpu_full)
     print(json.dumps(line))
 
 
