@@ -271,6 +271,23 @@ const char *mahi_batch_last_error(const mahi_batch *b);
 mahi_status mahi_autotune(int periodic, double edge, int64_t n_atoms, int precision, double target_rel_err,
                           double site_extent, int *order, int *depth);
 
+/* Measured choice of the launch shapes of one context (device work; blocks
+ * until done).  Times `reps` evaluations (after one warm-up each) of the
+ * positions `xyz` (device memory, the context's precision, [n_atoms][3], as
+ * with MAHI_DEVICE_IO) for each candidate and keeps the fastest:
+ *   - float32 contexts: the number of operator ranges of the main M2L launch
+ *     (1, 2, 3, 4, 5, 6 or 8; the default comes from a makespan model),
+ *   - the most near-field targets per lane (1, 2 or 3; default 3; each leaf
+ *     still picks its own count up to this cap by lane utilisation).
+ * Later evaluations of the context use the choices, which change results only
+ * by rounding (another grouping of the same sums).  Writes the choices to
+ * *m2l_ranges (0 for float64) and *p2p_targets when those are not NULL.
+ * The evaluations write the context's own buffers, not the caller's.
+ * Errors: MAHI_EINVAL (NULL ctx or xyz), MAHI_ERANGE (reps outside 1..1000),
+ * MAHI_ESTATE (lambda-tilde not set, or stage profiling open), MAHI_EDEVICE;
+ * on an error the context keeps its previous choices.                        */
+mahi_status mahi_tune(mahi_ctx *ctx, const void *xyz, int reps, int *m2l_ranges, int *p2p_targets);
+
 /* Release every host and device resource of the context (NULL is allowed). */
 void mahi_destroy(mahi_ctx *ctx);
 

@@ -38,6 +38,7 @@ struct mahi_ctx {
   int KS = 0;      // stride of one box's coefficients in the multipole/local arrays (>= (p+1)^2, zero padded)
   int n_cu = 256;  // compute units of the device
   M2LPlan plan32{};  // float32 M2L decomposition
+  int p2p_mmax = 3;  // most near-field targets per lane (mahi_tune may lower it)
   double ke = kDefaultKe;
   hipStream_t stream = nullptr;
   bool own_stream = false;
@@ -413,7 +414,7 @@ mahi_status eval_impl(mahi_ctx *ctx, const mahi_eval_args *a) {
   for (int l = std::max(hl, l2l_first); l <= d; ++l) launch_updown<T>(Lc, Tl2l, p, KS, l - 1, false, st);
   ctx->mark(6);
   launch_p2p<T>(tb.sorted, tb.sorted_lo, ctx->start, ctx->perm, Lc + level_offset(d) * KS, KS, ctx->geom, d, ctx->periodic, p, ctx->ke,
-                static_cast<T *>(ctx->phi_sorted), F, pot, ctx->epart, st);
+                static_cast<T *>(ctx->phi_sorted), F, pot, ctx->epart, st, ctx->p2p_mmax);
   ctx->mark(7);
   if (ctx->M > 0) {
     SiteArgs s = site_args<T>(ctx);
@@ -676,7 +677,7 @@ std::string packed_setup(mahi_batch *b, int maxa, int maxf) {
     S.p2p.p = p;
     S.p2p.K = K;
     S.p2p.KS = KS;
-    S.p2p.cap = 0;
+    S.p2p.mmax = 3;
     S.p2p.dloc = (size_t)4 * K * sizeof(float) <= 16384 ? 1 : 0;
     S.p2p.ke = x->ke;
   }
@@ -1286,6 +1287,81 @@ void mahi_batch_destroy(mahi_batch *b) {
 const char *mahi_batch_last_error(const mahi_batch *b) {
   if (!b) return g_create_error.c_str();
   return b->err.c_str();
+}
+
+mahi_status mahi_tune(mahi_ctx *ctx, const void *xyz, int reps, int *m2l_ranges, int *p2p_targets) {
+  if (!ctx) return MAHI_EINVAL;
+  if (!xyz) return ctx->fail(MAHI_EINVAL, "xyz is NULL");
+  if (reps < 1 || reps > 1000) return ctx->fail(MAHI_ERANGE, "reps must be in 1..1000");
+  if (!ctx->lambda_set) return ctx->fail(MAHI_ESTATE, "lambda-tilde not set");
+  if (ctx->prof_max > 0) return ctx->fail(MAHI_ESTATE, "stage profiling is open");
+  HIP_TRY(hipSetDevice(ctx->device), "set device");
+  // the context's own output buffers; forces and dE/dlambda-tilde as in a full evaluation
+  mahi_eval_args a{};
+  a.xyz = xyz;
+  a.forces = ctx->F;
+  a.energy = ctx->E;
+  a.dvdl = ctx->M > 0 ? ctx->dvdl : nullptr;
+  a.flags = MAHI_DEVICE_IO;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  HIP_TRY(hipEventCreate(&e0), "event");
+  if (hipEventCreate(&e1) != hipSuccess) {
+    (void)hipEventDestroy(e0);
+    return ctx->fail(MAHI_EDEVICE, "event");
+  }
+  auto timed = [&](float &ms) -> mahi_status {
+    mahi_status st = ctx->prec == 32 ? eval_impl<float>(ctx, &a) : eval_impl<double>(ctx, &a);  // warm-up
+    if (st != MAHI_OK) return st;
+    if (hipEventRecord(e0, ctx->stream) != hipSuccess) return ctx->fail(MAHI_EDEVICE, "event record");
+    for (int r = 0; r < reps && st == MAHI_OK; ++r)
+      st = ctx->prec == 32 ? eval_impl<float>(ctx, &a) : eval_impl<double>(ctx, &a);
+    if (st != MAHI_OK) return st;
+    if (hipEventRecord(e1, ctx->stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+        hipEventElapsedTime(&ms, e0, e1) != hipSuccess)
+      return ctx->fail(MAHI_EDEVICE, "event timing");
+    return MAHI_OK;
+  };
+  mahi_status st = MAHI_OK;
+  // float32 M2L: operator ranges of the main launch (the partial-sum array holds kM2LMaxSplit)
+  if (ctx->prec == 32 && ctx->plan32.ntiles > 0) {
+    const int keep = ctx->plan32.nsplit;
+    int best = keep;
+    float best_ms = 1e30f;
+    for (int ns : {1, 2, 3, 4, 5, 6, 8}) {
+      if (ns > kM2LMaxSplit) continue;
+      ctx->plan32.nsplit = ns;
+      float ms = 0.f;
+      st = timed(ms);
+      if (st != MAHI_OK) break;
+      if (ms < best_ms) {
+        best_ms = ms;
+        best = ns;
+      }
+    }
+    ctx->plan32.nsplit = st == MAHI_OK ? best : keep;
+  }
+  // near field: most targets per lane
+  if (st == MAHI_OK) {
+    const int keep = ctx->p2p_mmax;
+    int best = keep;
+    float best_ms = 1e30f;
+    for (int mm = 1; mm <= 3 && st == MAHI_OK; ++mm) {
+      ctx->p2p_mmax = mm;
+      float ms = 0.f;
+      st = timed(ms);
+      if (st == MAHI_OK && ms < best_ms) {
+        best_ms = ms;
+        best = mm;
+      }
+    }
+    ctx->p2p_mmax = st == MAHI_OK ? best : keep;
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (st != MAHI_OK) return st;
+  if (m2l_ranges) *m2l_ranges = ctx->prec == 32 ? ctx->plan32.nsplit : 0;
+  if (p2p_targets) *p2p_targets = ctx->p2p_mmax;
+  return MAHI_OK;
 }
 
 mahi_status mahi_autotune(int periodic, double edge, int64_t n_atoms, int precision, double target,

@@ -971,14 +971,14 @@ struct P2PPass {
   int P, G;  // targets per group row, source groups
 };
 
-__device__ __forceinline__ P2PPass p2p_pass_shape(int nt, int &M) {
+__device__ __forceinline__ P2PPass p2p_pass_shape(int nt, int mmax, int &M) {
   // lane utilisation nt * G / (64 M) for M = 1, 2, 3 (P = ceil(nt / M), G = 64 / P);
   // more targets per lane share each source load and loop step, so a larger M
   // is taken unless its utilisation is more than 0.06 below the current
   // choice's (measured on 30-atom leaves, where M = 1, 2 and 3 tie)
   int bestM = 1, bestG = 64 / max(nt, 1);
   float best = (float)nt * bestG / 64.f;
-  for (int m = 2; m <= 3; ++m) {
+  for (int m = 2; m <= min(mmax, 3); ++m) {
     const int P = (nt + m - 1) / m;
     const int G = 64 / max(P, 1);
     const float u = (float)nt * G / (64.f * m);
@@ -1396,7 +1396,7 @@ __device__ __forceinline__ void p2p_body(const Atom4<T> *__restrict__ sorted, co
   for (int tp = tb; tp < tb + nt_leaf; tp += 64) {
     const int nt = min(64, tb + nt_leaf - tp);
     int M;
-    const P2PPass ps = p2p_pass_shape(nt, M);
+    const P2PPass ps = p2p_pass_shape(nt, a.mmax, M);
     T acc[4] = {T(0), T(0), T(0), T(0)};
     if (p2p_tot <= kP2PFlatMax) {
       if (M == 1)
@@ -2142,7 +2142,7 @@ int p2p_blocks(int d) {
 template <class T>
 void launch_p2p(const Atom4<T> *sorted, const Atom4<T> *sorted_lo, const int *start, const int *perm, const T *Lleaf,
                 int KS, const Geom *g, int d, int periodic, int p, double ke, T *phi_sorted, T *F, T *pot_user,
-                double *epart, hipStream_t st) {
+                double *epart, hipStream_t st, int mmax) {
   P2PArgs a;
   a.KS = KS;
   a.d = d;
@@ -2150,7 +2150,7 @@ void launch_p2p(const Atom4<T> *sorted, const Atom4<T> *sorted_lo, const int *st
   a.p = p;
   a.K = (p + 1) * (p + 1);
   a.ke = ke;
-  a.cap = 0;
+  a.mmax = mmax;
   // gradient coefficients in LDS when L, Dx, Dy, Dz fit in 16 KB
   a.dloc = (size_t)4 * a.K * sizeof(T) <= 16384 ? 1 : 0;
   const size_t lds = (size_t)(a.dloc ? 4 : 1) * a.K * sizeof(T);
@@ -2310,7 +2310,7 @@ void launch_packed(const PackedPlan &pp, hipStream_t st) {
   template int updown_np<T>(int, bool);                                                                               \
   template int p2p_blocks<T>(int);                                                                                   \
   template void launch_p2p<T>(const Atom4<T> *, const Atom4<T> *, const int *, const int *, const T *, int,          \
-                              const Geom *, int, int, int, double, T *, T *, T *, double *, hipStream_t);            \
+                              const Geom *, int, int, int, double, T *, T *, T *, double *, hipStream_t, int);       \
   template void launch_charge_scale<T>(const SiteArgs &, const double *, T *, hipStream_t);                          \
   template void launch_site<T>(const SiteArgs &, const T *, const int *, const Geom *, const double *,               \
                                const SiteIO<T> &, hipStream_t);

@@ -29,7 +29,7 @@ struct XArgs {
 };
 
 struct P2PArgs {
-  int d, periodic, p, K, KS, cap, dloc;
+  int d, periodic, p, K, KS, mmax, dloc;  // mmax: most targets per lane in a near-field pass (1..3)
   double ke;
 };
 
@@ -159,7 +159,7 @@ template <class T> int p2p_blocks(int d);
 template <class T>
 void launch_p2p(const Atom4<T> *sorted, const Atom4<T> *sorted_lo, const int *start, const int *perm, const T *Lleaf,
                 int KS, const Geom *g, int d, int periodic, int p, double ke, T *phi_sorted, T *F, T *pot_user,
-                double *epart, hipStream_t st);
+                double *epart, hipStream_t st, int mmax = 3);
 template <class T> void launch_charge_scale(const SiteArgs &s, const double *lam, T *qt, hipStream_t st);
 template <class T>
 void launch_site(const SiteArgs &s, const T *xyz, const int *slot_of, const Geom *g, const double *LamT,

@@ -130,6 +130,8 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.mahi_autotune.argtypes = [ctypes.c_int, ctypes.c_double, ctypes.c_int64, ctypes.c_int, ctypes.c_double,
                                   ctypes.c_double, ip, ip]
     lib.mahi_autotune.restype = ctypes.c_int
+    lib.mahi_tune.argtypes = [vp, vp, ctypes.c_int, ip, ip]
+    lib.mahi_tune.restype = ctypes.c_int
     return lib
 
 
@@ -324,6 +326,15 @@ class Mahi:
         args = _CorrectArgs(xyz_ptr, potential_ptr, energy_ptr or None, forces_ptr or None, dvdl_ptr or None,
                             dedq_ptr or None, MAHI_DEVICE_IO)
         _check(self._lib.mahi_correct_noalloc(self._h, ctypes.byref(args)), self._h)
+
+    def tune(self, xyz_ptr: int, reps: int = 3):
+        """Measured choice of the M2L operator ranges and the near-field targets per
+        lane for positions at device pointer xyz_ptr (mahi_tune); blocks until done.
+        Returns (m2l_ranges, p2p_targets)."""
+        r, t = ctypes.c_int(), ctypes.c_int()
+        _check(self._lib.mahi_tune(self._h, ctypes.c_void_p(xyz_ptr), int(reps), ctypes.byref(r), ctypes.byref(t)),
+               self._h)
+        return r.value, t.value
 
     def profile_begin(self, max_evals: int):
         _check(self._lib.mahi_profile_begin(self._h, int(max_evals)), self._h)
