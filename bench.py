@@ -37,6 +37,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_FP32_MATRIX_TFLOPS = 157.3
+PEAK_HBM_GBS = 8000.0
 PEAK_FP64_MATRIX_TFLOPS = 78.6
 PEAK_FP32_VECTOR_TFLOPS = 157.3
 # float32 vector ALU without packed operations (which this build does not emit):
@@ -339,6 +340,16 @@ def main():
         "p2p_pairs": pairs,
         "p2p_gflops": 20.0 * pairs / (stages["p2p_l2p"] * 1e-3) / 1e9,
     }
+    m2l_traffic = measured_traffic("m2l_traffic.txt")
+    p2p_traffic = measured_traffic("p2p_traffic.txt")
+
+    def hbm(traffic, stage_ms):
+        # achieved HBM bandwidth of the kernel from its counter-measured bytes, against the 8 TB/s peak
+        if traffic is None:
+            return {"hbm_gbs": None, "hbm_frac": None}
+        gbs = traffic / (stage_ms * 1e-3) / 1e9
+        return {"hbm_gbs": gbs, "hbm_frac": gbs / PEAK_HBM_GBS}
+
     line = {
         "metric": "ns/eval (E,F,dV/dlambda) at 1M atoms+512 sites, FP32 vs FP64, MAHI overhead %",
         "value": t32 * 1e9,
@@ -356,13 +367,14 @@ def main():
                                "(1,004,296 atoms), depth 5, order 8", "n_atoms": s.n_atoms,
                    "sites": len(s.sites), "forms": s.n_forms, "depth": s.depth, "order": s.order},
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": PEAK_FP32_MATRIX_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / PEAK_FP32_MATRIX_TFLOPS, "traffic": measured_traffic("m2l_traffic.txt"),
-                     "kernel": "m2l", "flop_per_launch": m2l_flop},
+                     "frac": achieved / PEAK_FP32_MATRIX_TFLOPS, "traffic": m2l_traffic,
+                     "kernel": "m2l", "flop_per_launch": m2l_flop, **hbm(m2l_traffic, stages["m2l"])},
         "roofline_p2p": {"bound": "alu", "achieved": p2p_tflops, "peak": PEAK_FP32_VECTOR_UNPACKED_TFLOPS,
                          "unit": "TFLOP/s", "frac": p2p_tflops / PEAK_FP32_VECTOR_UNPACKED_TFLOPS,
-                         "traffic": measured_traffic("p2p_traffic.txt"), "kernel": "p2p_l2p",
+                         "traffic": p2p_traffic, "kernel": "p2p_l2p",
                          "flop_per_launch": 20.0 * pairs,
-                         "frac_of_pair_instruction_bound": pairs / P2P_PAIR_BOUND_PER_S / (stages["p2p_l2p"] * 1e-3)},
+                         "frac_of_pair_instruction_bound": pairs / P2P_PAIR_BOUND_PER_S / (stages["p2p_l2p"] * 1e-3),
+                         **hbm(p2p_traffic, stages["p2p_l2p"])},
         "extra": extra,
     }
     if not args.no_batch:
