@@ -55,6 +55,7 @@ struct mahi_ctx {
   void *packed = nullptr;  // leaf-local atoms in input order (octree build)
   void *packed_lo = nullptr, *sorted_lo = nullptr;  // float32 above order 8: coordinate residuals
   void *Mc = nullptr, *Lc = nullptr, *m2l = nullptr, *m2m = nullptr, *l2l = nullptr, *sorted = nullptr;
+  void *m2m16 = nullptr, *l2l16 = nullptr;  // float32, orders up to 8: matrix-core M2M/L2L operator stacks
   double *LamT = nullptr, *qds = nullptr, *epart = nullptr, *dE_site = nullptr, *dvdl = nullptr, *E = nullptr;
   double *bbox = nullptr, *lam = nullptr, *fq = nullptr;
   double *dedq = nullptr, *dvdl_qi = nullptr, *E_qi = nullptr;  // host-I/O staging of the optional outputs
@@ -262,6 +263,15 @@ mahi_status setup_device(mahi_ctx *ctx, const std::vector<double> &q_env, const 
     HIP_TRY(ctx->alloc(ctx->l2l, sizeof(T) * dn.size()), "alloc l2l");
     HIP_TRY(hipMemcpy(ctx->m2m, up.data(), sizeof(T) * up.size(), hipMemcpyHostToDevice), "upload m2m");
     HIP_TRY(hipMemcpy(ctx->l2l, dn.data(), sizeof(T) * dn.size(), hipMemcpyHostToDevice), "upload l2l");
+    if (f32 && K <= 81 && KS == 88) {
+      std::vector<float> up16(updown16_table_size(true)), dn16(updown16_table_size(false));
+      updown16_table(K, pu, true, up16.data());
+      updown16_table(K, pd, false, dn16.data());
+      HIP_TRY(ctx->alloc(ctx->m2m16, sizeof(float) * up16.size()), "alloc m2m");
+      HIP_TRY(ctx->alloc(ctx->l2l16, sizeof(float) * dn16.size()), "alloc l2l");
+      HIP_TRY(hipMemcpy(ctx->m2m16, up16.data(), sizeof(float) * up16.size(), hipMemcpyHostToDevice), "upload m2m");
+      HIP_TRY(hipMemcpy(ctx->l2l16, dn16.data(), sizeof(float) * dn16.size(), hipMemcpyHostToDevice), "upload l2l");
+    }
   }
   const int lmin = ctx->periodic ? 1 : 2;
   if (d >= lmin) {
@@ -385,6 +395,22 @@ mahi_status eval_impl(mahi_ctx *ctx, const mahi_eval_args *a) {
   const int l2l_first = ctx->periodic ? 1 : 3;
   const int hl = std::max(lmin, d - 1);
   const T *Tm2m = static_cast<const T *>(ctx->m2m), *Tl2l = static_cast<const T *>(ctx->l2l);
+  // M2M (up) into parent_level, or L2L (down) out of it.  The two deepest
+  // levels' translations on the main stream run on the matrix cores; the
+  // upper levels' ones on the second stream stay on the vector ALU, whose
+  // blocks start in the main M2L launch's last round instead of taking
+  // matrix-core cycles from it (measured: main M2L 0.94 -> 0.99 ms when the
+  // upper levels used the matrix cores too).
+  auto updown = [&](T *X, const T *Tab, int parent_level, bool up, hipStream_t s) {
+    if constexpr (sizeof(T) == sizeof(float)) {
+      const void *t16 = up ? ctx->m2m16 : ctx->l2l16;
+      if (t16 && s == st) {
+        launch_updown16(X, static_cast<const float *>(t16), parent_level, up, s);
+        return;
+      }
+    }
+    launch_updown<T>(X, Tab, p, KS, parent_level, up, s);
+  };
   auto m2l = [&](int lo, int hi, hipStream_t s) {
     if (d < lmin || lo > hi) return;
     if constexpr (sizeof(T) == sizeof(float))
@@ -395,23 +421,23 @@ mahi_status eval_impl(mahi_ctx *ctx, const mahi_eval_args *a) {
   };
   // only the deepest M2M (parent level d - 1) precedes the fork: the main M2L
   // needs multipoles of levels d - 1 and d only
-  if (d - 1 >= mlow) launch_updown<T>(Mc, Tm2m, p, KS, d - 1, true, st);
+  if (d - 1 >= mlow) updown(Mc, Tm2m, d - 1, true, st);
   ctx->mark(3);
   HIP_TRY(hipEventRecord(ctx->ev_fork, st), "fork");
   HIP_TRY(hipStreamWaitEvent(ctx->side, ctx->ev_fork, 0), "fork");
   ctx->mark_side(0);
   if (ctx->periodic) launch_moments(ctx->qds, nleaf, ctx->qds + 5 * (int64_t)nleaf, ctx->side);
-  for (int l = d - 2; l >= mlow; --l) launch_updown<T>(Mc, Tm2m, p, KS, l, true, ctx->side);
+  for (int l = d - 2; l >= mlow; --l) updown(Mc, Tm2m, l, true, ctx->side);
   m2l(lmin, hl - 1, ctx->side);
   if (ctx->periodic) launch_lattice<T>(Mc, Lc, ctx->LamT, ncoef(p), ctx->qds + 5 * (int64_t)nleaf, ctx->geom, ctx->side);
-  for (int l = l2l_first; l <= std::min(hl - 1, d); ++l) launch_updown<T>(Lc, Tl2l, p, KS, l - 1, false, ctx->side);
+  for (int l = l2l_first; l <= std::min(hl - 1, d); ++l) updown(Lc, Tl2l, l - 1, false, ctx->side);
   ctx->mark_side(1);
   HIP_TRY(hipEventRecord(ctx->ev_join, ctx->side), "join");
   ctx->mark(4);
   m2l(hl, d, st);
   ctx->mark(5);
   HIP_TRY(hipStreamWaitEvent(st, ctx->ev_join, 0), "join");
-  for (int l = std::max(hl, l2l_first); l <= d; ++l) launch_updown<T>(Lc, Tl2l, p, KS, l - 1, false, st);
+  for (int l = std::max(hl, l2l_first); l <= d; ++l) updown(Lc, Tl2l, l - 1, false, st);
   ctx->mark(6);
   launch_p2p<T>(tb.sorted, tb.sorted_lo, ctx->start, ctx->perm, Lc + level_offset(d) * KS, KS, ctx->geom, d, ctx->periodic, p, ctx->ke,
                 static_cast<T *>(ctx->phi_sorted), F, pot, ctx->epart, st, ctx->p2p_mmax);

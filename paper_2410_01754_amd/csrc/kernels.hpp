@@ -148,6 +148,10 @@ void launch_m2l_f32(const float *M, float *L, float *part, const float *Tab, con
 void m2l32_table(const M2LPlan &a, int slot, const double *Tv, float *dst);
 size_t m2l32_table_size(const M2LPlan &a, int nslots);
 template <class T> void updown_table(int K, int KS, const double *const *Tc, T *A);
+// float32 M2M/L2L on the matrix cores for orders up to 8 (rows of 88 floats)
+size_t updown16_table_size(bool up);
+void updown16_table(int K, const double *const *Tc, bool up, float *dst);
+void launch_updown16(float *X, const float *A, int parent_level, bool up, hipStream_t st);
 template <class T> size_t updown_lds(int KS, bool up);
 template <class T> int updown_np(int KS, bool up);  // parents per block of k_updown
 template <class T> void launch_updown(T *X, const T *A, int p, int KS, int parent_level, bool up, hipStream_t st);

@@ -584,6 +584,175 @@ void launch_packed_m2l(const PackedPlan &pp, hipStream_t st) {
 
 // Host layout of the float32 M2L operator table: [slot][row group][chunk][r][96]
 // where LDS row r = 2s + h of a chunk holds k = 8(s/4) + 4h + s%4.
+// ---------------------------------------------------------------------------
+// M2M and L2L in float32 on the matrix cores, for orders up to 8 (K <= 81
+// coefficients in rows padded to 88).  The children of parent P are the
+// consecutive boxes 8P .. 8P+7, so both translations of a level are products
+// with one operator stack:
+//   M2M: M[P] (rows 0..87)        = sum_c T_c M[8P + c]
+//   L2L: L[8P .. 8P+7] (704 rows) += S L[P],  S = the 8 operators S_c stacked
+// A block of 4 waves takes 16 parents, the 16 columns of every 16x16x4 tile.
+// Lane (q = lane / 16, c = lane % 16) holds parent c; in k-step s (21 per
+// product) it contracts k = 20q + s (s < 20) or 80 + q (s = 20), so that its
+// inputs are five float4 runs and one value, and pad rows of the inputs meet
+// zero operator columns.  Operators are stored in the order the lanes read
+// them: per 16-row tile, steps 0..19 as [s / 4][lane][s % 4] and step 20 as
+// [lane], zero outside K x K.  Lane (q, c) ends with rows 4q .. 4q+3 of the
+// tile for parent c.
+//   M2M: wave w contracts children 2w and 2w + 1 into the 6 row tiles (rows
+//   0..95, zero from K on); the four waves' tiles are added through LDS in
+//   wave order and rows 0..87 written (pad rows as zeros).
+//   L2L: wave w owns row tiles 11w .. 11w+10 of the 704 child rows and adds
+//   them to the children in place (pad rows add zero).
+// ---------------------------------------------------------------------------
+constexpr int kUDRows = 88;          // padded coefficient rows of a box
+constexpr int kUDTile = 21 * 64;     // floats of one operator tile in lane order
+constexpr int kUDUpTiles = 6;        // M2M output rows 0..95
+constexpr int kUDDnTiles = 44;       // L2L output rows: 8 children x 88
+constexpr int kUDDnPerWave = 11;
+
+__device__ __forceinline__ void ud_load_in(const float *__restrict__ src, int q, float *b) {
+  const floatx4 *s4 = reinterpret_cast<const floatx4 *>(src + 20 * q);
+#pragma unroll
+  for (int g = 0; g < 5; ++g) {
+    const floatx4 v = s4[g];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) b[4 * g + j] = v[j];
+  }
+  b[20] = q == 0 ? src[80] : 0.f;
+}
+
+struct UDTile {
+  floatx4 a[5];
+  float a20;
+};
+
+__device__ __forceinline__ void ud_load_tile(const float *__restrict__ tile, int lane, UDTile &r) {
+  const floatx4 *a4 = reinterpret_cast<const floatx4 *>(tile) + lane;
+#pragma unroll
+  for (int g = 0; g < 5; ++g) r.a[g] = a4[64 * g];
+  r.a20 = tile[1280 + lane];
+}
+
+__device__ __forceinline__ floatx4 ud_product(const UDTile &t, const float *b, floatx4 acc) {
+#pragma unroll
+  for (int g = 0; g < 5; ++g)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc = __builtin_amdgcn_mfma_f32_16x16x4f32(t.a[g][j], b[4 * g + j], acc, 0, 0, 0);
+  return __builtin_amdgcn_mfma_f32_16x16x4f32(t.a20, b[20], acc, 0, 0, 0);
+}
+
+__global__ void __launch_bounds__(256) k_m2m16(float *__restrict__ X, const float *__restrict__ A,
+                                               int64_t off_parent, int64_t off_child, int64_t nparent) {
+  __shared__ floatx4 red[4][kUDUpTiles][64];
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, q = lane >> 4, c = lane & 15;
+  const int64_t P = (int64_t)blockIdx.x * 16 + c;
+  const int64_t Pr = P < nparent ? P : 0;  // lanes past the last parent read parent 0 and write nothing
+  floatx4 acc[kUDUpTiles];
+#pragma unroll
+  for (int t = 0; t < kUDUpTiles; ++t) acc[t] = floatx4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    const int ch = 2 * wave + h;
+    float b[21];
+    ud_load_in(X + (off_child + 8 * Pr + ch) * kUDRows, q, b);
+    const float *At = A + (size_t)ch * kUDUpTiles * kUDTile;
+    UDTile cur, nxt;
+    ud_load_tile(At, lane, cur);
+#pragma unroll
+    for (int t = 0; t < kUDUpTiles; ++t) {
+      if (t + 1 < kUDUpTiles) ud_load_tile(At + (t + 1) * kUDTile, lane, nxt);
+      acc[t] = ud_product(cur, b, acc[t]);
+      if (t + 1 < kUDUpTiles) cur = nxt;
+    }
+  }
+#pragma unroll
+  for (int t = 0; t < kUDUpTiles; ++t) red[wave][t][lane] = acc[t];
+  __syncthreads();
+  for (int e = threadIdx.x; e < kUDUpTiles * 64; e += 256) {
+    const int t = e >> 6, l = e & 63;
+    const int row = 16 * t + 4 * (l >> 4);
+    const int64_t Pp = (int64_t)blockIdx.x * 16 + (l & 15);
+    if (row < kUDRows && Pp < nparent) {
+      floatx4 v = red[0][t][l];
+      v += red[1][t][l];
+      v += red[2][t][l];
+      v += red[3][t][l];
+      *reinterpret_cast<floatx4 *>(X + (off_parent + Pp) * kUDRows + row) = v;
+    }
+  }
+}
+
+__global__ void __launch_bounds__(256) k_l2l16(float *__restrict__ X, const float *__restrict__ A,
+                                               int64_t off_parent, int64_t off_child, int64_t nparent) {
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, q = lane >> 4, c = lane & 15;
+  const int64_t P = (int64_t)blockIdx.x * 16 + c;
+  const bool valid = P < nparent;
+  float b[21];
+  ud_load_in(X + (off_parent + (valid ? P : 0)) * kUDRows, q, b);
+  float *dst = X + (off_child + 8 * (valid ? P : 0)) * kUDRows + 4 * q;
+  const float *At = A + (size_t)wave * kUDDnPerWave * kUDTile;
+  UDTile cur, nxt;
+  ud_load_tile(At, lane, cur);
+#pragma unroll
+  for (int i = 0; i < kUDDnPerWave; ++i) {
+    if (i + 1 < kUDDnPerWave) ud_load_tile(At + (i + 1) * kUDTile, lane, nxt);
+    const floatx4 r = ud_product(cur, b, floatx4{0.f, 0.f, 0.f, 0.f});
+    if (valid) {
+      floatx4 *d4 = reinterpret_cast<floatx4 *>(dst + 16 * (kUDDnPerWave * wave + i));
+      floatx4 v = *d4;
+      v += r;
+      *d4 = v;
+    }
+    if (i + 1 < kUDDnPerWave) cur = nxt;
+  }
+}
+
+size_t updown16_table_size(bool up) { return (size_t)(up ? 8 * kUDUpTiles : kUDDnTiles) * kUDTile; }
+
+// Lane-order stacks of k_m2m16 ([child][tile], T_c) and k_l2l16 ([tile], S_c
+// of the child that owns the row); Tc[c] holds the K x K operator row-major.
+void updown16_table(int K, const double *const *Tc, bool up, float *dst) {
+  auto tile = [&](float *blk, auto elem) {
+    for (int lane = 0; lane < 64; ++lane) {
+      const int q = lane >> 4, c = lane & 15;
+      for (int s = 0; s < 21; ++s) {
+        const int k = s < 20 ? 20 * q + s : 80 + q;
+        const float v = k < K ? elem(c, k) : 0.f;
+        if (s < 20) blk[((s >> 2) * 64 + lane) * 4 + (s & 3)] = v;
+        else blk[1280 + lane] = v;
+      }
+    }
+  };
+  if (up) {
+    for (int ch = 0; ch < 8; ++ch)
+      for (int t = 0; t < kUDUpTiles; ++t)
+        tile(dst + (size_t)(ch * kUDUpTiles + t) * kUDTile, [&](int c, int k) {
+          const int r = 16 * t + c;
+          return r < K ? (float)Tc[ch][(size_t)r * K + k] : 0.f;
+        });
+  } else {
+    for (int t = 0; t < kUDDnTiles; ++t)
+      tile(dst + (size_t)t * kUDTile, [&](int c, int k) {
+        const int R = 16 * t + c, ch = R / kUDRows, r = R % kUDRows;
+        return r < K ? (float)Tc[ch][(size_t)r * K + k] : 0.f;
+      });
+  }
+}
+
+// parent_level: M2M writes that level from its children; L2L adds into the
+// level below it.  X holds rows of 88 floats per box.
+void launch_updown16(float *X, const float *A, int parent_level, bool up, hipStream_t st) {
+  const int64_t nparent = int64_t(1) << (3 * parent_level);
+  const dim3 grid((unsigned)((nparent + 15) / 16)), block(256);
+  if (up)
+    hipLaunchKernelGGL(k_m2m16, grid, block, 0, st, X, A, level_offset(parent_level), level_offset(parent_level + 1),
+                       nparent);
+  else
+    hipLaunchKernelGGL(k_l2l16, grid, block, 0, st, X, A, level_offset(parent_level), level_offset(parent_level + 1),
+                       nparent);
+}
+
 void m2l32_table(const M2LPlan &a, int slot, const double *Tv, float *dst) {
   if (a.ns == 21) {
     // k_m2l16_f32, per slot: steps 0..19 [s/4][q][t][c][s%4], step 20 [q][t][c], row 80 [q][24]
