@@ -10,8 +10,11 @@ Reported next to the headline ns/eval:
   * the float64 GPU path on the same system (FP32 speedup),
   * the plain FMM on the same scaled charges with no sites (MAHI overhead %),
   * per-stage mean durations from HIP events recorded on the library's stream
-    over the timed region, and the roofline of the dominant kernel (M2L) and
-    of the near field (P2P + L2P, bound by the vector ALU),
+    in a second pass of K evaluations (the headline pass records no events:
+    each event between two kernels leaves a gap on the stream), and the
+    roofline of the dominant kernel (M2L) and of the near field (P2P + L2P,
+    bound by the vector ALU), with their HBM traffic from the committed
+    counter profiles,
   * the site correction alone (mahi_correct) on a given potential,
   * a batch of 96 small systems (3k..60k atoms, autotuned order and depth):
     per-system latency and the packed batch's throughput (extra.batch96),
