@@ -195,9 +195,13 @@ def cpu_baseline(system, full: bool = False):
         system's splitting parameter, so that n_k and the table keep their
         full sizes (and their cache behaviour); extrapolated linearly in N;
       * the real-space sums: per target a cell-list walk at full density.
-        Timed for 16,384 sampled targets of the full system with the
-        reciprocal sums switched off (no k-vectors), scaled by N / 16,384;
+        Timed for 8,192 and 16,384 sampled targets of the full system with
+        the reciprocal sums switched off (no k-vectors) and extrapolated
+        linearly to N targets (the cell list over all atoms is a per-call
+        cost, not a per-target one);
       * the per-site pair sums of the HI step, timed in full.
+    The same parts on one thread (smaller samples) give single_thread_value;
+    cpu_model names the host CPU.
     With full=True the oracle also runs on the whole workload (minutes)."""
     import ctypes
     from oracle import ewald, hi
@@ -217,17 +221,26 @@ def cpu_baseline(system, full: bool = False):
         ks.append((int(idx.shape[0]), time.perf_counter() - t0))
     slope = (ks[1][1] - ks[0][1]) / (ks[1][0] - ks[0][0])
     t_recip = ks[0][1] + slope * (N - ks[0][0])
-    T = min(16384, N)
-    tg = np.sort(rng.choice(N, T, replace=False)).astype(np.int64)
-    phi, fld = np.zeros(T), np.zeros((T, 3))
     lib = ewald._load()
-    t0 = time.perf_counter()
-    rcode = lib.ew_field(N, ewald._ptr(x), ewald._ptr(qt), L, alpha, rc, 0, T, ewald._ptr(tg, ctypes.c_int64),
-                         ewald._ptr(phi), ewald._ptr(fld), th)
-    t_real_s = time.perf_counter() - t0
-    if rcode != 0:
-        raise RuntimeError("oracle real-space sample failed")
-    t_real = t_real_s * N / T
+    tg_all = rng.permutation(N).astype(np.int64)
+
+    def real_sample(T, threads):
+        # real-space sums (no k-vectors) for the first T of the shuffled targets
+        tg = np.ascontiguousarray(np.sort(tg_all[:T]))
+        phi, fld = np.zeros(T), np.zeros((T, 3))
+        t0 = time.perf_counter()
+        rcode = lib.ew_field(N, ewald._ptr(x), ewald._ptr(qt), L, alpha, rc, 0, T, ewald._ptr(tg, ctypes.c_int64),
+                             ewald._ptr(phi), ewald._ptr(fld), threads)
+        if rcode != 0:
+            raise RuntimeError("oracle real-space sample failed")
+        return time.perf_counter() - t0
+
+    # two target counts, so that the per-call set-up (the cell list over all N
+    # atoms) is not scaled with the targets
+    T = min(16384, N)
+    rs = [(T // 2, real_sample(T // 2, th)), (T, real_sample(T, th))]
+    t_real_s = rs[1][1]
+    t_real = rs[0][1] + (rs[1][1] - rs[0][1]) / (rs[1][0] - rs[0][0]) * (N - rs[0][0])
     d = np.concatenate([(x[st.atoms][:, None, :] - x[st.atoms][None, :, :]).reshape(-1, 3) for st in system.sites])
     t0 = time.perf_counter()
     ewald.pair(d, L, nthreads=th)
@@ -237,15 +250,45 @@ def cpu_baseline(system, full: bool = False):
            "sample": (f"the oracle on {th} threads, full system scaled part by part: reciprocal sums timed on "
                       f"{ks[0][0]} and {ks[1][0]} atoms of the full box with its splitting parameter "
                       f"({ks[0][1]:.2f} s, {ks[1][1]:.2f} s; n_k at full size, linear in N -> {t_recip:.0f} s), "
-                      f"real-space sums for {T} sampled targets of the full system ({t_real_s:.2f} s -> "
-                      f"{t_real:.0f} s), site pair sums {t_pair:.2f} s; "
+                      f"real-space sums for {T // 2} and {T} sampled targets of the full system ({rs[0][1]:.2f} s, "
+                      f"{t_real_s:.2f} s; linear in the targets -> {t_real:.0f} s), site pair sums {t_pair:.2f} s; "
                       f"{time.perf_counter() - t_start:.0f} s of sampling"),
            "parts_s": {"reciprocal": t_recip, "real": t_real, "site_pairs": t_pair}}
+    # one thread: the same parts on smaller samples (1/1024 and 1/512 of the
+    # atoms for the reciprocal sums, 256 and 512 targets for the real-space sums)
+    ks1 = []
+    for frac in (1024, 512):
+        idx = np.sort(rng.choice(N, N // frac, replace=False))
+        t0 = time.perf_counter()
+        ewald.field(x[idx], qt[idx], L, alpha=alpha, nthreads=1)
+        ks1.append((int(idx.shape[0]), time.perf_counter() - t0))
+    slope1 = (ks1[1][1] - ks1[0][1]) / (ks1[1][0] - ks1[0][0])
+    T1 = min(512, N)
+    rs1 = [(T1 // 2, real_sample(T1 // 2, 1)), (T1, real_sample(T1, 1))]
+    t_real1 = rs1[0][1] + (rs1[1][1] - rs1[0][1]) / (rs1[1][0] - rs1[0][0]) * (N - rs1[0][0])
+    t_one = ks1[0][1] + slope1 * (N - ks1[0][0]) + t_real1 + t_pair * th
+    out["single_thread_value"] = t_one * 1e9
+    out["single_thread_sample"] = (f"one thread: reciprocal sums on {ks1[0][0]} and {ks1[1][0]} atoms "
+                                   f"-> {ks1[0][1] + slope1 * (N - ks1[0][0]):.0f} s, real-space sums for {T1 // 2} "
+                                   f"and {T1} targets -> {t_real1:.0f} s, site pairs scaled by the thread count")
+    out["cpu_model"] = cpu_model()
     if full:
         t0 = time.perf_counter()
         hi.hi_periodic(system.x, system.q, system.sites, system.box, nthreads=th)
         out["measured_full_value"] = (time.perf_counter() - t0) * 1e9
     return out
+
+
+def cpu_model() -> str:
+    """The host CPU's model name (first processor entry of /proc/cpuinfo)."""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
 
 
 def main():

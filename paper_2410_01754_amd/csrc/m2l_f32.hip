@@ -1,7 +1,9 @@
-// Float32 M2L on the matrix cores (paper, section "Fast Multipole Method":
-// the multipole-to-local translation of the far field, for every box of
-// levels 1..d (periodic) or 2..d (open) over its 189-box interaction list).
-// Kernels, the work decomposition (M2LPlan) and the operator table layout.
+// Float32 translations on the matrix cores (paper, section "Fast Multipole
+// Method"): the multipole-to-local translation of the far field, for every
+// box of levels 1..d (periodic) or 2..d (open) over its 189-box interaction
+// list (kernels, the work decomposition M2LPlan and the operator table
+// layout), and the upward and downward passes between the two deepest
+// levels (M2M, L2L) for orders up to 8.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
